@@ -1,0 +1,188 @@
+/*
+ * sptucker.h - C ABI of the MI355X (gfx950) sparse Tucker library.
+ *
+ * The library computes the hot path of sparse Tucker decomposition by higher-order orthogonal
+ * iteration with QR column pivoting (Kaya-style sparse HOOI as stated in "Sparse Tucker Tensor
+ * Decomposition on a Hybrid FPGA-CPU Platform", arXiv 2010.10638):
+ *   - per mode n, the sparse tensor-times-matrix chain (TTMc) of Alg. 2:
+ *       Y_(n)(i_n, :) += x * (U_t1(i_t1, :) kron U_t2(i_t2, :) kron ...)   over the nonzeros,
+ *     other modes t != n ascending, the LAST one varying fastest (Sec. III-C, Kronecker listing);
+ *   - U_n <- the first R_n columns of Q from a QR with column pivoting of Y_(n) (Sec. III-D),
+ *     or of Y_(n) Y_(n)^T when Y_(n) has more columns than rows;
+ *   - after the mode loop, the core G_(N) = U_N^T Y_(N) (Alg. 2; unfolded form in Sec. III-B);
+ *   - the fit 1 - ||X - G x_1 U_1 ... x_N U_N|| / ||X||.
+ *
+ * Conventions for every entry point:
+ *   - Plain C types only.  "device" pointers are HIP device memory (hipMalloc or a PyTorch CUDA
+ *     tensor); "host" pointers are ordinary host memory.  Every pointer argument is owned by the
+ *     caller; the library owns only what hangs off a tk_ctx and frees it in tucker_free.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).  Work is enqueued
+ *     asynchronously on it; only the calls documented as synchronising wait for the device.
+ *   - Indices are 0-based.  Modes are 0-based in the API (mode 0 is the paper's mode 1).
+ *   - Matrices are row-major: U_k is I_k x R_k, Y_(n) is I_n x K_n with K_n = prod_{t != n} R_t.
+ *   - The core G is stored C-order (last index fastest), R_1 x ... x R_N.
+ *   - Return value: TK_OK or an error code; tucker_last_error() gives a message (thread-local).
+ *     Arguments are validated before any launch.  A HIP failure, including an asynchronous
+ *     fault of earlier work on the stream that surfaces during the call, returns TK_ERR_HIP.
+ */
+#ifndef SPTUCKER_H
+#define SPTUCKER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tk_ctx tk_ctx;
+
+enum tk_status {
+    TK_OK = 0,
+    TK_ERR_ARG = 1,          /* invalid argument (null pointer, bad mode, rank out of range, ...) */
+    TK_ERR_RANGE = 2,        /* a coordinate lies outside [0, I_k) */
+    TK_ERR_OOM = 3,          /* device allocation failed */
+    TK_ERR_HIP = 4,          /* a HIP runtime call or kernel failed */
+    TK_ERR_UNSUPPORTED = 5   /* valid input outside this build's limits (see TK_MAX_*) */
+};
+
+/* Arithmetic of the TTMc (the QRP, core and fit always run in FP64):
+ *   TK_F64  - FP64 values, factors, products and accumulation; Y_(n) is double.
+ *   TK_F32  - FP32 values and factor copies, FP32 products and accumulation; Y_(n) is float.
+ *   TK_BF16 - BF16 values and factor copies, FP32 products (exact: a product of three bf16
+ *             numbers fits the fp32 significand) and FP32 accumulation; Y_(n) is float. */
+enum tk_dtype { TK_F64 = 0, TK_F32 = 1, TK_BF16 = 2 };
+
+/* tucker_init flags */
+#define TK_FLAG_NO_FAT_RULE 0x1u     /* factor a fat Y_(n) directly instead of Y_(n) Y_(n)^T */
+
+#define TK_MAX_ORDER 8               /* 2 <= N <= TK_MAX_ORDER */
+#define TK_MAX_KCOLS 4096            /* K_n = prod_{t != n} R_t must not exceed this */
+
+/*
+ * tucker_init - take a COO tensor and build the per-mode sorted layout (Alg. 2 input: the sparse
+ * tensor and the ranks R_1..R_N; COO format of Sec. III-A / Table I).
+ *   out     host   receives the new context
+ *   order   N, 2..TK_MAX_ORDER
+ *   dims    host   int64[N], I_k >= 1, with prod I_k < 2^63
+ *   ranks   host   int32[N], 1 <= R_k <= I_k and R_k <= K_k (the QRP needs R_k columns)
+ *   nnz     number of COO entries, 0 <= nnz < 2^31
+ *   coords  device int32[N * nnz], structure of arrays: coords[k * nnz + p] = i_k of entry p
+ *   vals    device double[nnz]
+ *   dtype   enum tk_dtype for the TTMc
+ *   flags   TK_FLAG_*
+ * Duplicate coordinates are summed (in input order, FP64); explicit zeros are kept.  The inputs
+ * are copied; the caller may free them after the call returns.  Synchronises the stream once (to
+ * size the layout).  Errors: TK_ERR_ARG, TK_ERR_RANGE (no context is created), TK_ERR_OOM,
+ * TK_ERR_UNSUPPORTED, TK_ERR_HIP.
+ */
+int tucker_init(tk_ctx** out, int order, const int64_t* dims, const int32_t* ranks, int64_t nnz,
+                const int32_t* coords, const double* vals, int dtype, uint32_t flags, void* stream);
+
+/*
+ * tucker_get_info - sizes of the layout built by tucker_init (host outputs, any may be NULL):
+ *   nnz_distinct  number of distinct coordinates
+ *   rows          int64[N]: number of distinct i_n per mode (non-empty rows of Y_(n))
+ *   chunks        int64[N]: number of nonzero chunks the TTMc kernels walk per mode
+ *   normx2        ||X||_F^2 of the coalesced values (FP64)
+ */
+int tucker_get_info(const tk_ctx* ctx, int64_t* nnz_distinct, int64_t* rows, int64_t* chunks,
+                    double* normx2);
+
+/*
+ * tucker_get_csf - copy the mode-sorted layout of one mode to caller device buffers.  The sort key
+ * is (i_n, other modes ascending) for N <= 3 and (i_n, i_f, remaining others ascending) for
+ * N >= 4, where the fiber mode f is the last mode other than n.
+ *   rows  device int32[S]      distinct i_n, ascending (S = rows[mode] of tucker_get_info)
+ *   ptr   device int64[S + 1]  row pointers into the sorted nonzeros
+ *   idx   device int32[(N-1) * nnz_distinct], other-mode indices, other modes ascending (SoA)
+ *   vals  device, nnz_distinct values in the TTMc storage type (double / float / bf16 bits)
+ */
+int tucker_get_csf(tk_ctx* ctx, int mode, int32_t* rows, int64_t* ptr, int32_t* idx, void* vals,
+                   void* stream);
+
+/*
+ * ttmc_mode - Y_(n) = X_(n) (kron_{t != n} U_t): the nonzero loop of Alg. 2 for one mode, the
+ * per-nonzero Kronecker update of Sec. III-C.
+ *   mode  0..N-1
+ *   U     host array of N device pointers to FP64 factors (I_k x R_k); U[mode] is not read
+ *   Y     device, I_n x K_n row-major: double for TK_F64, float otherwise.  Every entry is written
+ *         (rows without nonzeros are set to zero).
+ * The factors are converted to the context's TTMc precision on the stream before the product.
+ */
+int ttmc_mode(tk_ctx* ctx, int mode, const double* const* U, void* Y, void* stream);
+
+/*
+ * qrp_update - U_n <- QRP(Y_(n), R_n) (Alg. 2; Sec. III-D): the first R_n columns of Q of a QR
+ * with column pivoting, in FP64.  When K_n > I_n (and TK_FLAG_NO_FAT_RULE is not set) the QRP is
+ * taken of Y_(n) Y_(n)^T.  Q is the Householder one: column j has the sign that the reflector
+ * v = x + sgn(x_0) ||x|| e_1 (sgn(0) = +1) gives it.
+ *   Y     device I_n x K_n (double for TK_F64, float otherwise)
+ *   U_out device double I_n x R_n
+ *   piv   device int32[R_n] or NULL: original column index chosen at each pivot step
+ * Also refreshes the context's low-precision copy of U_n used by hooi_sweep.
+ */
+int qrp_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, int32_t* piv, void* stream);
+
+/*
+ * core_fit - G_(N) = U_N^T Y_(N) (Alg. 2, the step after the mode loop) and the fit.
+ *   Y_last device I_N x K_N (context Y type) computed with the final U_1..U_{N-1}
+ *   U_last device double I_N x R_N (orthonormal columns)
+ *   G      device double[prod R_k], C-order: G[r_1..r_{N-1}, r_N] = G_(N)[r_N, c(r_1..r_{N-1})]
+ *   fit    device double scalar or NULL: 1 - sqrt(max(||X||^2 - ||G||^2, 0)) / ||X||
+ */
+int core_fit(tk_ctx* ctx, const void* Y_last, const double* U_last, double* G, double* fit,
+             void* stream);
+
+/*
+ * hooi_sweep - one sweep of Alg. 2: for n = 0..N-1, TTMc with the current factors then
+ * U_n <- QRP(Y_(n), R_n) (modes updated in order, each using the factors already refreshed in this
+ * sweep); then the core and the fit.
+ *   U        host array of N device pointers to double I_k x R_k, read and overwritten
+ *   G        device double[prod R_k] (C-order), overwritten
+ *   fit_dev  device double scalar or NULL
+ *   fit_host host double or NULL; when non-NULL the call synchronises the stream to return it
+ * The Y_(n) buffers are owned by the context.
+ */
+int hooi_sweep(tk_ctx* ctx, double* const* U, double* G, double* fit_dev, double* fit_host,
+               void* stream);
+
+/*
+ * reconstruct - the Tucker model at sampled coordinates (paper Sec. III, the model
+ * X ~ G x_1 U_1 ... x_N U_N):  out[p] = sum_r G[r] prod_k U_k(i_k(p), r_k), in FP64.
+ *   G       device double[prod R_k] C-order
+ *   U       host array of N device pointers to double I_k x R_k
+ *   m       number of coordinates (0 allowed)
+ *   coords  device int32[N * m] (SoA, 0-based; each must lie in [0, I_k) - not checked here)
+ *   out     device double[m]
+ */
+int reconstruct(tk_ctx* ctx, const double* G, const double* const* U, int64_t m,
+                const int32_t* coords, double* out, void* stream);
+
+/*
+ * tucker_profile - start (capacity > 0) or stop (capacity = 0) timing the regions of hooi_sweep.
+ * While on, each sweep records HIP events on its stream around every mode's TTMc (kernel and
+ * split-row fix-up), every QRP and the core/fit; at most `capacity` sweeps are recorded.  The
+ * events are created here, so recording adds no allocation to the sweep.  Errors: TK_ERR_ARG,
+ * TK_ERR_HIP.
+ */
+int tucker_profile(tk_ctx* ctx, int capacity);
+
+/*
+ * tucker_profile_read - synchronise the recorded events and return the summed region times in
+ * milliseconds since tucker_profile was switched on (host outputs, any may be NULL):
+ *   ttmc_ms  double[N]   per-mode TTMc time     qrp_ms  double[N]   per-mode QRP time
+ *   core_ms  double      core and fit           sweeps  int64       sweeps recorded
+ */
+int tucker_profile_read(tk_ctx* ctx, double* ttmc_ms, double* qrp_ms, double* core_ms, int64_t* sweeps);
+
+/* tucker_free - synchronise the last stream used, release every context allocation.  NULL is ok. */
+void tucker_free(tk_ctx* ctx);
+
+/* tucker_last_error - message for the last non-OK status returned on this host thread. */
+const char* tucker_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPTUCKER_H */

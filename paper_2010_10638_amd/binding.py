@@ -1,0 +1,247 @@
+"""ctypes binding of libsptucker.so: same entry points as include/sptucker.h, taking torch tensors.
+
+Argument marshalling only: every step of the decomposition runs in the HIP library.  The library
+must be built (``python paper_2010_10638_amd/build.py`` or ``__graft_entry__.build()``); loading
+fails loudly otherwise - there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libsptucker.so")
+
+TK_OK, TK_ERR_ARG, TK_ERR_RANGE, TK_ERR_OOM, TK_ERR_HIP, TK_ERR_UNSUPPORTED = range(6)
+TK_F64, TK_F32, TK_BF16 = 0, 1, 2
+TK_FLAG_NO_FAT_RULE = 0x1
+DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
+_STATUS = {1: "TK_ERR_ARG", 2: "TK_ERR_RANGE", 3: "TK_ERR_OOM", 4: "TK_ERR_HIP", 5: "TK_ERR_UNSUPPORTED"}
+
+EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "core_fit",
+           "hooi_sweep", "reconstruct", "tucker_profile", "tucker_profile_read", "tucker_free",
+           "tucker_last_error")
+
+
+class TuckerError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsptucker.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build the HIP library first "
+                          "(python paper_2010_10638_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    P, I, I64, U32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32
+    lib.tucker_init.argtypes = [ctypes.POINTER(P), I, P, P, I64, P, P, I, U32, P]
+    lib.tucker_get_info.argtypes = [P, P, P, P, P]
+    lib.tucker_get_csf.argtypes = [P, I, P, P, P, P, P]
+    lib.ttmc_mode.argtypes = [P, I, P, P, P]
+    lib.qrp_update.argtypes = [P, I, P, P, P, P]
+    lib.core_fit.argtypes = [P, P, P, P, P, P]
+    lib.hooi_sweep.argtypes = [P, P, P, P, P, P]
+    lib.reconstruct.argtypes = [P, P, P, I64, P, P, P]
+    lib.tucker_profile.argtypes = [P, I]
+    lib.tucker_profile_read.argtypes = [P, P, P, P, P]
+    lib.tucker_free.argtypes = [P]
+    lib.tucker_free.restype = None
+    lib.tucker_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("tucker_free", "tucker_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != TK_OK:
+        msg = load_library().tucker_last_error().decode(errors="replace")
+        raise TuckerError(status, msg)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptrs(mats, n, skip=None, name="U"):
+    arr = (ctypes.c_void_p * n)()
+    for k in range(n):
+        if k == skip:
+            arr[k] = None
+            continue
+        arr[k] = _dev(mats[k], torch.float64, f"{name}[{k}]").value
+    return arr
+
+
+class Ctx:
+    """Handle returned by tucker_init; holds the shapes needed to marshal later calls."""
+
+    def __init__(self, handle, dims, ranks, dtype):
+        self.handle = ctypes.c_void_p(handle)
+        self.dims = [int(d) for d in dims]
+        self.ranks = [int(r) for r in ranks]
+        self.dtype = dtype
+        self.order = len(self.dims)
+
+    def K(self, mode: int) -> int:
+        k = 1
+        for t, r in enumerate(self.ranks):
+            if t != mode:
+                k *= r
+        return k
+
+    @property
+    def ytype(self):
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and self.handle.value and _lib is not None:
+            _lib.tucker_free(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+
+def tucker_init(coords: torch.Tensor, vals: torch.Tensor, dims, ranks, dtype: str = "f32",
+                fat_rule: bool = True) -> Ctx:
+    """coords: int32 [N, nnz] (0-based), vals: float64 [nnz], both on the GPU."""
+    lib = load_library()
+    N = len(dims)
+    if coords.dim() != 2 or coords.shape[0] != N:
+        raise ValueError("coords must be [N, nnz]")
+    nnz = int(coords.shape[1])
+    if vals.numel() != nnz:
+        raise ValueError("vals must have nnz entries")
+    d = (ctypes.c_int64 * N)(*[int(x) for x in dims])
+    r = (ctypes.c_int32 * N)(*[int(x) for x in ranks])
+    h = ctypes.c_void_p()
+    flags = 0 if fat_rule else TK_FLAG_NO_FAT_RULE
+    cp = _dev(coords, torch.int32, "coords") if nnz else None
+    vp = _dev(vals, torch.float64, "vals") if nnz else None
+    _check(lib.tucker_init(ctypes.byref(h), N, d, r, nnz, cp, vp, DTYPES[dtype], flags, _stream()))
+    return Ctx(h.value, dims, ranks, dtype)
+
+
+def tucker_get_info(ctx: Ctx) -> dict:
+    lib = load_library()
+    nnz = ctypes.c_int64()
+    rows = (ctypes.c_int64 * ctx.order)()
+    chunks = (ctypes.c_int64 * ctx.order)()
+    nx2 = ctypes.c_double()
+    _check(lib.tucker_get_info(ctx.handle, ctypes.byref(nnz), rows, chunks, ctypes.byref(nx2)))
+    return dict(nnz=nnz.value, rows=list(rows), chunks=list(chunks), normx2=nx2.value)
+
+
+def tucker_get_csf(ctx: Ctx, mode: int) -> dict:
+    info = tucker_get_info(ctx)
+    S, D, N = info["rows"][mode], info["nnz"], ctx.order
+    dev = torch.device("cuda")
+    rows = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+    ptr = torch.empty(S + 1, dtype=torch.int64, device=dev)
+    idx = torch.empty((N - 1, max(D, 1)), dtype=torch.int32, device=dev)
+    vt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.int16}[ctx.dtype]
+    vals = torch.empty(max(D, 1), dtype=vt, device=dev)
+    _check(load_library().tucker_get_csf(ctx.handle, mode, ctypes.c_void_p(rows.data_ptr()),
+                                         ctypes.c_void_p(ptr.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
+                                         ctypes.c_void_p(vals.data_ptr()), _stream()))
+    return dict(rows=rows[:S], ptr=ptr, idx=idx[:, :D], vals=vals[:D])
+
+
+def ttmc_mode(ctx: Ctx, mode: int, U, Y: torch.Tensor | None = None) -> torch.Tensor:
+    if Y is None:
+        Y = torch.empty((ctx.dims[mode], ctx.K(mode)), dtype=ctx.ytype, device="cuda")
+    yp = _dev(Y, ctx.ytype, "Y")
+    if tuple(Y.shape) != (ctx.dims[mode], ctx.K(mode)):
+        raise ValueError("Y has the wrong shape")
+    _check(load_library().ttmc_mode(ctx.handle, mode, _ptrs(U, ctx.order, skip=mode), yp, _stream()))
+    return Y
+
+
+def qrp_update(ctx: Ctx, mode: int, Y: torch.Tensor, U_out: torch.Tensor | None = None,
+               piv: torch.Tensor | None = None):
+    if U_out is None:
+        U_out = torch.empty((ctx.dims[mode], ctx.ranks[mode]), dtype=torch.float64, device="cuda")
+    if piv is None:
+        piv = torch.empty(ctx.ranks[mode], dtype=torch.int32, device="cuda")
+    _check(load_library().qrp_update(ctx.handle, mode, _dev(Y, ctx.ytype, "Y"),
+                                     _dev(U_out, torch.float64, "U_out"), _dev(piv, torch.int32, "piv"),
+                                     _stream()))
+    return U_out, piv
+
+
+def core_fit(ctx: Ctx, Y_last: torch.Tensor, U_last: torch.Tensor, G: torch.Tensor | None = None,
+             fit: torch.Tensor | None = None):
+    if G is None:
+        G = torch.empty(ctx.ranks, dtype=torch.float64, device="cuda")
+    if fit is None:
+        fit = torch.empty(1, dtype=torch.float64, device="cuda")
+    _check(load_library().core_fit(ctx.handle, _dev(Y_last, ctx.ytype, "Y_last"),
+                                   _dev(U_last, torch.float64, "U_last"), _dev(G, torch.float64, "G"),
+                                   _dev(fit, torch.float64, "fit"), _stream()))
+    return G, fit
+
+
+def hooi_sweep(ctx: Ctx, U, G: torch.Tensor | None = None, fit: torch.Tensor | None = None,
+               sync_fit: bool = False):
+    """One sweep; U (list of float64 CUDA tensors) is updated in place.  Returns (G, fit) where fit
+    is a device tensor, or a Python float when sync_fit."""
+    if G is None:
+        G = torch.empty(ctx.ranks, dtype=torch.float64, device="cuda")
+    if fit is None:
+        fit = torch.empty(1, dtype=torch.float64, device="cuda")
+    host = ctypes.c_double()
+    _check(load_library().hooi_sweep(ctx.handle, _ptrs(U, ctx.order), _dev(G, torch.float64, "G"),
+                                     _dev(fit, torch.float64, "fit"),
+                                     ctypes.byref(host) if sync_fit else None, _stream()))
+    return G, (host.value if sync_fit else fit)
+
+
+def reconstruct(ctx: Ctx, G: torch.Tensor, U, coords: torch.Tensor, out: torch.Tensor | None = None):
+    m = int(coords.shape[1])
+    if out is None:
+        out = torch.empty(m, dtype=torch.float64, device="cuda")
+    if m == 0:
+        return out
+    _check(load_library().reconstruct(ctx.handle, _dev(G, torch.float64, "G"), _ptrs(U, ctx.order), m,
+                                      _dev(coords, torch.int32, "coords"), _dev(out, torch.float64, "out"),
+                                      _stream()))
+    return out
+
+
+def tucker_profile(ctx: Ctx, capacity: int):
+    _check(load_library().tucker_profile(ctx.handle, int(capacity)))
+
+
+def tucker_profile_read(ctx: Ctx) -> dict:
+    N = ctx.order
+    tt = (ctypes.c_double * N)()
+    qq = (ctypes.c_double * N)()
+    cc = ctypes.c_double()
+    ns = ctypes.c_int64()
+    _check(load_library().tucker_profile_read(ctx.handle, tt, qq, ctypes.byref(cc), ctypes.byref(ns)))
+    return dict(ttmc_ms=list(tt), qrp_ms=list(qq), core_ms=cc.value, sweeps=ns.value)
+
+
+def tucker_free(ctx: Ctx):
+    if ctx.handle.value:
+        load_library().tucker_free(ctx.handle)
+        ctx.handle = ctypes.c_void_p(None)

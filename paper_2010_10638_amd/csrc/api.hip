@@ -1,0 +1,338 @@
+// C ABI entry points (include/sptucker.h): argument validation, context lifetime, workspace
+// sizing, and the sweep driver of Alg. 2.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace tk {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_error(hipError_t e, const char* what) {
+    (void)hipGetLastError();
+    return set_error(e == hipErrorOutOfMemory ? TK_ERR_OOM : TK_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int qrp_route(const tk_ctx* ctx, int mode);
+
+namespace {
+
+int dmalloc(void** p, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return set_error(TK_ERR_OOM, "device allocation of %zu bytes failed", bytes);
+    }
+    return TK_OK;
+}
+
+void free_events(tk_ctx* c) {
+    if (c->prof_ev) {
+        const int per = 2 * c->N + 2;
+        for (int i = 0; i < c->prof_cap * per; ++i)
+            if (c->prof_ev[i]) (void)hipEventDestroy(c->prof_ev[i]);
+        delete[] c->prof_ev;
+    }
+    c->prof_ev = nullptr;
+    c->prof_cap = 0;
+    c->prof_used = 0;
+}
+
+void free_ctx(tk_ctx* c) {
+    if (!c) return;
+    free_events(c);
+    for (int m = 0; m < kMaxOrder; ++m) {
+        ModeLayout& ml = c->mode[m];
+        void* ps[] = {ml.rows, ml.ptr, ml.idx, ml.val, ml.chunk_ptr, ml.chunk_row, ml.chunk_slot, ml.split};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        if (c->Ulp[m]) (void)hipFree(c->Ulp[m]);
+    }
+    void* ws[] = {c->ws.y, c->ws.carry, c->ws.qrp, c->ws.qrp_int, c->ws.scal};
+    for (void* p : ws)
+        if (p) (void)hipFree(p);
+    delete c;
+}
+
+int check_ctx(const tk_ctx* c) {
+    if (!c) return set_error(TK_ERR_ARG, "null context");
+    return TK_OK;
+}
+
+int check_mode(const tk_ctx* c, int mode) {
+    if (mode < 0 || mode >= c->N) return set_error(TK_ERR_ARG, "mode %d outside [0, %d)", mode, c->N);
+    return TK_OK;
+}
+
+// Surface asynchronous faults of earlier work before enqueueing more.
+int pending_error() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "earlier device work");
+    return TK_OK;
+}
+
+}  // namespace
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+const char* tucker_last_error(void) { return tk::g_err; }
+
+int tucker_init(tk_ctx** out, int order, const int64_t* dims, const int32_t* ranks, int64_t nnz,
+                const int32_t* coords, const double* vals, int dtype, uint32_t flags, void* stream) {
+    if (!out) return set_error(TK_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (order < 2 || order > kMaxOrder) return set_error(TK_ERR_ARG, "order %d outside [2, %d]", order, kMaxOrder);
+    if (!dims || !ranks) return set_error(TK_ERR_ARG, "dims/ranks is null");
+    if (dtype != TK_F64 && dtype != TK_F32 && dtype != TK_BF16) return set_error(TK_ERR_ARG, "bad dtype %d", dtype);
+    if (nnz < 0) return set_error(TK_ERR_ARG, "negative nnz");
+    if (nnz >= (int64_t)1 << 31) return set_error(TK_ERR_UNSUPPORTED, "nnz %lld >= 2^31", (long long)nnz);
+    if (nnz > 0 && (!coords || !vals)) return set_error(TK_ERR_ARG, "coords/vals is null");
+    if (flags & ~TK_FLAG_NO_FAT_RULE) return set_error(TK_ERR_ARG, "unknown flags 0x%x", flags);
+    double log2prod = 0.0;
+    for (int t = 0; t < order; ++t) {
+        if (dims[t] < 1) return set_error(TK_ERR_ARG, "dims[%d] = %lld < 1", t, (long long)dims[t]);
+        if (dims[t] >= ((int64_t)1 << 31)) return set_error(TK_ERR_UNSUPPORTED, "dims[%d] >= 2^31", t);
+        if (ranks[t] < 1 || ranks[t] > dims[t])
+            return set_error(TK_ERR_ARG, "ranks[%d] = %d outside [1, I_%d = %lld]", t, ranks[t], t, (long long)dims[t]);
+        log2prod += std::log2((double)dims[t]);
+    }
+    if (log2prod >= 62.999) return set_error(TK_ERR_UNSUPPORTED, "prod(dims) must be below 2^63");
+    for (int n = 0; n < order; ++n) {
+        int64_t K = 1;
+        for (int t = 0; t < order; ++t)
+            if (t != n) K *= ranks[t];
+        if (K > kMaxK) return set_error(TK_ERR_UNSUPPORTED, "K_%d = %lld exceeds %d", n, (long long)K, kMaxK);
+        if (ranks[n] > K) return set_error(TK_ERR_ARG, "ranks[%d] = %d exceeds K_%d = %lld", n, ranks[n], n, (long long)K);
+    }
+    int st = pending_error();
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    tk_ctx* c = new tk_ctx();
+    c->N = order;
+    c->dtype = dtype;
+    c->flags = flags;
+    for (int t = 0; t < order; ++t) {
+        c->dims[t] = dims[t];
+        c->ranks[t] = ranks[t];
+    }
+    (void)hipGetDevice(&c->device);
+    st = build_layout(c, coords, vals, nnz, s);
+    if (st) { free_ctx(c); return st; }
+    // factor copies and workspaces
+    size_t ybytes = 0, cbytes = 0, qbytes = core_workspace_bytes(c);
+    int64_t maxn = 0;
+    for (int t = 0; t < order; ++t) {
+        c->ldU[t] = pad_rank(ranks[t]);
+        if ((st = dmalloc(&c->Ulp[t], (size_t)dims[t] * c->ldU[t] * dtype_size(dtype)))) { free_ctx(c); return st; }
+        if ((st = fill_zero(c->Ulp[t], (size_t)dims[t] * c->ldU[t] * dtype_size(dtype), s))) { free_ctx(c); return st; }
+        const ModeLayout& ml = c->mode[t];
+        ybytes = std::max(ybytes, (size_t)dims[t] * ml.K * ytype_size(dtype));
+        cbytes = std::max(cbytes, (size_t)ml.ncarry * ml.K * ytype_size(dtype));
+        qbytes = std::max(qbytes, qrp_workspace_bytes(c, t));
+        maxn = std::max<int64_t>(maxn, std::max<int64_t>(ml.K, dims[t]));
+    }
+    c->ws.y_bytes = ybytes;
+    c->ws.carry_bytes = cbytes;
+    c->ws.qrp_bytes = qbytes;
+    c->ws.qrp_int_bytes = (size_t)(64 + maxn) * 4;
+    if ((st = dmalloc(&c->ws.y, ybytes)) || (st = dmalloc(&c->ws.carry, cbytes)) ||
+        (st = dmalloc((void**)&c->ws.qrp, qbytes)) || (st = dmalloc((void**)&c->ws.qrp_int, c->ws.qrp_int_bytes)) ||
+        (st = dmalloc((void**)&c->ws.scal, 16 * sizeof(double)))) {
+        free_ctx(c);
+        return st;
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { free_ctx(c); return hip_error(e, "tucker_init"); }
+    c->last_stream = s;
+    *out = c;
+    return TK_OK;
+}
+
+int tucker_get_info(const tk_ctx* ctx, int64_t* nnz_distinct, int64_t* rows, int64_t* chunks, double* normx2) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (nnz_distinct) *nnz_distinct = ctx->nnz;
+    for (int m = 0; m < ctx->N; ++m) {
+        if (rows) rows[m] = ctx->mode[m].S;
+        if (chunks) chunks[m] = ctx->mode[m].nchunks;
+    }
+    if (normx2) *normx2 = ctx->normx2;
+    return TK_OK;
+}
+
+int tucker_get_csf(tk_ctx* ctx, int mode, int32_t* rows, int64_t* ptr, int32_t* idx, void* vals, void* stream) {
+    int st = check_ctx(ctx);
+    if (st || (st = check_mode(ctx, mode))) return st;
+    const ModeLayout& ml = ctx->mode[mode];
+    hipStream_t s = (hipStream_t)stream;
+    if (ml.S > 0 && !rows) return set_error(TK_ERR_ARG, "rows is null");
+    if (!ptr) return set_error(TK_ERR_ARG, "ptr is null");
+    if (ctx->nnz > 0 && (!idx || !vals)) return set_error(TK_ERR_ARG, "idx/vals is null");
+    if (ml.S > 0) TK_HIP(hipMemcpyAsync(rows, ml.rows, (size_t)ml.S * 4, hipMemcpyDeviceToDevice, s));
+    // widen the int32 row pointers on the host side of the copy (init-time data, small)
+    std::vector<int32_t> h32((size_t)ml.S + 1);
+    std::vector<int64_t> h64((size_t)ml.S + 1);
+    TK_HIP(hipMemcpyAsync(h32.data(), ml.ptr, h32.size() * 4, hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < h32.size(); ++i) h64[i] = h32[i];
+    TK_HIP(hipMemcpyAsync(ptr, h64.data(), h64.size() * 8, hipMemcpyHostToDevice, s));
+    if (ctx->nnz > 0) {
+        TK_HIP(hipMemcpyAsync(idx, ml.idx, (size_t)ctx->nnz * 4 * (ctx->N - 1), hipMemcpyDeviceToDevice, s));
+        TK_HIP(hipMemcpyAsync(vals, ml.val, (size_t)ctx->nnz * dtype_size(ctx->dtype), hipMemcpyDeviceToDevice, s));
+    }
+    TK_HIP(hipStreamSynchronize(s));
+    ctx->last_stream = s;
+    return TK_OK;
+}
+
+int ttmc_mode(tk_ctx* ctx, int mode, const double* const* U, void* Y, void* stream) {
+    int st = check_ctx(ctx);
+    if (st || (st = check_mode(ctx, mode))) return st;
+    if (!U || !Y) return set_error(TK_ERR_ARG, "U/Y is null");
+    for (int t = 0; t < ctx->N; ++t)
+        if (t != mode && !U[t]) return set_error(TK_ERR_ARG, "U[%d] is null", t);
+    if ((st = pending_error())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    for (int t = 0; t < ctx->N; ++t)
+        if (t != mode && (st = convert_factor(ctx, t, U[t], s))) return st;
+    st = ttmc_run(ctx, mode, Y, s);
+    ctx->last_stream = s;
+    return st;
+}
+
+int qrp_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, int32_t* piv, void* stream) {
+    int st = check_ctx(ctx);
+    if (st || (st = check_mode(ctx, mode))) return st;
+    if (!Y || !U_out) return set_error(TK_ERR_ARG, "Y/U_out is null");
+    if ((st = pending_error())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = qrp_run(ctx, mode, Y, U_out, piv, s);
+    ctx->last_stream = s;
+    return st;
+}
+
+int core_fit(tk_ctx* ctx, const void* Y_last, const double* U_last, double* G, double* fit, void* stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!Y_last || !U_last || !G) return set_error(TK_ERR_ARG, "Y_last/U_last/G is null");
+    if ((st = pending_error())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = core_run(ctx, Y_last, U_last, G, fit, s);
+    ctx->last_stream = s;
+    return st;
+}
+
+int hooi_sweep(tk_ctx* ctx, double* const* U, double* G, double* fit_dev, double* fit_host, void* stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!U || !G) return set_error(TK_ERR_ARG, "U/G is null");
+    for (int t = 0; t < ctx->N; ++t)
+        if (!U[t]) return set_error(TK_ERR_ARG, "U[%d] is null", t);
+    if ((st = pending_error())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // mode 0 reads U_1..U_{N-1}; U_0's copy is rewritten by its own QRP before any later use
+    for (int t = 1; t < ctx->N; ++t)
+        if ((st = convert_factor(ctx, t, U[t], s))) return st;
+    double* fit = (fit_dev || !fit_host) ? fit_dev : ctx->ws.scal;
+    // events: [ttmc start, ttmc end = qrp start] per mode, then qrp end of the last mode, core end
+    hipEvent_t* ev = nullptr;
+    if (ctx->prof_ev && ctx->prof_used < ctx->prof_cap)
+        ev = ctx->prof_ev + (size_t)(ctx->prof_used++) * (2 * ctx->N + 2);
+    for (int n = 0; n < ctx->N; ++n) {
+        if (ev) TK_HIP(hipEventRecord(ev[2 * n], s));
+        if ((st = ttmc_run(ctx, n, ctx->ws.y, s))) return st;
+        if (ev) TK_HIP(hipEventRecord(ev[2 * n + 1], s));
+        if ((st = qrp_run(ctx, n, ctx->ws.y, U[n], nullptr, s))) return st;
+    }
+    if (ev) TK_HIP(hipEventRecord(ev[2 * ctx->N], s));
+    if ((st = core_run(ctx, ctx->ws.y, U[ctx->N - 1], G, fit, s))) return st;
+    if (ev) TK_HIP(hipEventRecord(ev[2 * ctx->N + 1], s));
+    ctx->last_stream = s;
+    if (fit_host) {
+        TK_HIP(hipMemcpyAsync(fit_host, fit, 8, hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+    }
+    return TK_OK;
+}
+
+int reconstruct(tk_ctx* ctx, const double* G, const double* const* U, int64_t m, const int32_t* coords,
+                double* out, void* stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (m < 0) return set_error(TK_ERR_ARG, "negative m");
+    if (m > 0 && (!G || !U || !coords || !out)) return set_error(TK_ERR_ARG, "null argument");
+    for (int t = 0; m > 0 && t < ctx->N; ++t)
+        if (!U[t]) return set_error(TK_ERR_ARG, "U[%d] is null", t);
+    if ((st = pending_error())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = reconstruct_run(ctx, G, U, m, coords, out, s);
+    ctx->last_stream = s;
+    return st;
+}
+
+int tucker_profile(tk_ctx* ctx, int capacity) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (capacity < 0) return set_error(TK_ERR_ARG, "negative capacity");
+    if (ctx->last_stream || ctx->prof_ev) (void)hipStreamSynchronize(ctx->last_stream);
+    free_events(ctx);
+    if (capacity == 0) return TK_OK;
+    const int per = 2 * ctx->N + 2;
+    ctx->prof_ev = new hipEvent_t[(size_t)capacity * per]();
+    ctx->prof_cap = capacity;
+    for (int i = 0; i < capacity * per; ++i) TK_HIP(hipEventCreate(&ctx->prof_ev[i]));
+    return TK_OK;
+}
+
+int tucker_profile_read(tk_ctx* ctx, double* ttmc_ms, double* qrp_ms, double* core_ms, int64_t* sweeps) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    const int N = ctx->N, per = 2 * N + 2;
+    double tt[kMaxOrder] = {}, qq[kMaxOrder] = {}, cc = 0.0;
+    for (int k = 0; k < ctx->prof_used; ++k) {
+        hipEvent_t* ev = ctx->prof_ev + (size_t)k * per;
+        TK_HIP(hipEventSynchronize(ev[per - 1]));
+        float ms = 0.f;
+        for (int n = 0; n < N; ++n) {
+            TK_HIP(hipEventElapsedTime(&ms, ev[2 * n], ev[2 * n + 1]));
+            tt[n] += ms;
+            TK_HIP(hipEventElapsedTime(&ms, ev[2 * n + 1], (n + 1 < N) ? ev[2 * n + 2] : ev[2 * N]));
+            qq[n] += ms;
+        }
+        TK_HIP(hipEventElapsedTime(&ms, ev[2 * N], ev[2 * N + 1]));
+        cc += ms;
+    }
+    for (int n = 0; n < N; ++n) {
+        if (ttmc_ms) ttmc_ms[n] = tt[n];
+        if (qrp_ms) qrp_ms[n] = qq[n];
+    }
+    if (core_ms) *core_ms = cc;
+    if (sweeps) *sweeps = ctx->prof_used;
+    return TK_OK;
+}
+
+void tucker_free(tk_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->last_stream);
+    free_ctx(ctx);
+}
+
+}  // extern "C"

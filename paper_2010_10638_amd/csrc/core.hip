@@ -1,0 +1,193 @@
+// Core tensor and fit (paper Alg. 2, the step after the mode loop; Sec. III-B unfolded form
+// G_(N) = U_N^T Y_(N)), sampled reconstruction of the Tucker model, factor conversions.
+#include "internal.h"
+
+namespace tk {
+
+namespace {
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+__global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t words) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < words;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0u;
+}
+
+template <typename LT>
+__global__ void k_convert_factor(const double* __restrict__ U, int64_t I, int R, int ld, LT* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= I * ld) return;
+    const int64_t i = e / ld;
+    const int c = (int)(e % ld);
+    const double u = (c < R) ? U[i * R + c] : 0.0;
+    if constexpr (sizeof(LT) == 8) out[e] = u;
+    else if constexpr (sizeof(LT) == 4) out[e] = (float)u;
+    else out[e] = f32_to_bf16((float)u);
+}
+
+// part[split][r][c] = sum_{i in slab} U[i][r] * Y[i][c]; thread per column c, 16 r's per z-block.
+template <typename YT>
+__global__ __launch_bounds__(256) void k_core_partial(const YT* __restrict__ Y, const double* __restrict__ U,
+                                                      int64_t I, int K, int R, int64_t slab,
+                                                      double* __restrict__ part) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int split = blockIdx.y;
+    const int rb = blockIdx.z * 16;
+    const int64_t i0 = (int64_t)split * slab;
+    const int64_t i1 = min(I, i0 + slab);
+    double acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+    if (c < K) {
+        for (int64_t i = i0; i < i1; ++i) {
+            const double y = (double)Y[i * K + c];
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (rb + r < R) acc[r] += U[i * R + rb + r] * y;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (rb + r < R) part[((int64_t)split * R + rb + r) * K + c] = acc[r];
+    }
+}
+
+// G[c * R + r] = sum_split part[split][r][c] in split order; then ||G||^2 and the fit.
+__global__ __launch_bounds__(1024) void k_core_finish(const double* __restrict__ part, int nsplit, int K, int R,
+                                                      double normx2, double* __restrict__ G,
+                                                      double* __restrict__ fit) {
+    __shared__ double red[16];
+    double g2 = 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)K * R; e += blockDim.x) {
+        const int c = (int)(e / R), r = (int)(e % R);
+        double s = 0.0;
+        for (int k = 0; k < nsplit; ++k) s += part[((int64_t)k * R + r) * K + c];
+        G[e] = s;
+        g2 += s * s;
+    }
+    for (int o = 32; o > 0; o >>= 1) g2 += __shfl_xor(g2, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g2;
+    __syncthreads();
+    if (threadIdx.x == 0 && fit) {
+        double s = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+        double r2 = normx2 - s;
+        if (r2 < 0.0) r2 = 0.0;
+        *fit = (normx2 > 0.0) ? 1.0 - sqrt(r2) / sqrt(normx2) : 0.0;
+    }
+}
+
+struct ReconArgs {
+    const double* U[kMaxOrder];
+    int32_t R[kMaxOrder];
+    int N;
+    int64_t size;
+};
+
+// One thread per coordinate; the core is walked in C order (last index fastest) with an
+// odometer that recomputes only the prefix products whose digit changed.
+__global__ void k_reconstruct(ReconArgs a, const double* __restrict__ G, int64_t m,
+                              const int32_t* __restrict__ coords, double* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m) return;
+    const double* row[kMaxOrder];
+    int r[kMaxOrder];
+    double pre[kMaxOrder + 1];
+    const int N = a.N;
+    for (int t = 0; t < N; ++t) {
+        row[t] = a.U[t] + (int64_t)coords[(int64_t)t * m + p] * a.R[t];
+        r[t] = 0;
+    }
+    pre[0] = 1.0;
+    for (int t = 0; t < N; ++t) pre[t + 1] = pre[t] * row[t][0];
+    double sum = 0.0;
+    for (int64_t g = 0; g < a.size; ++g) {
+        sum += G[g] * pre[N];
+        int t = N - 1;
+        while (t >= 0) {
+            if (++r[t] < a.R[t]) break;
+            r[t] = 0;
+            --t;
+        }
+        if (t < 0) break;
+        for (int u = t; u < N; ++u) pre[u + 1] = pre[u] * row[u][r[u]];
+    }
+    out[p] = sum;
+}
+
+}  // namespace
+
+int fill_zero(void* p, size_t bytes, hipStream_t s) {
+    const int64_t words = (int64_t)(bytes / 4);
+    if (words == 0) return TK_OK;
+    k_fill_zero<<<std::min<unsigned>(2048, cdiv(words, 256)), 256, 0, s>>>((uint32_t*)p, words);
+    TK_LAUNCH_CHECK("k_fill_zero");
+    return TK_OK;
+}
+
+int convert_factor(tk_ctx* ctx, int k, const double* U, hipStream_t s) {
+    const int64_t I = ctx->dims[k];
+    const int R = ctx->ranks[k], ld = ctx->ldU[k];
+    const unsigned g = cdiv(I * ld, 256);
+    if (ctx->dtype == TK_F64) k_convert_factor<double><<<g, 256, 0, s>>>(U, I, R, ld, (double*)ctx->Ulp[k]);
+    else if (ctx->dtype == TK_F32) k_convert_factor<float><<<g, 256, 0, s>>>(U, I, R, ld, (float*)ctx->Ulp[k]);
+    else k_convert_factor<bf16_t><<<g, 256, 0, s>>>(U, I, R, ld, (bf16_t*)ctx->Ulp[k]);
+    TK_LAUNCH_CHECK("k_convert_factor");
+    return TK_OK;
+}
+
+static void core_plan(const tk_ctx* ctx, int& nsplit, int64_t& slab) {
+    const int n = ctx->N - 1;
+    const int64_t I = ctx->dims[n];
+    const int64_t K = ctx->mode[n].K;
+    const int64_t cblocks = (K + 255) / 256;
+    nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(cblocks, 1), (I + 63) / 64));
+    slab = (I + nsplit - 1) / nsplit;
+    nsplit = (int)((I + slab - 1) / slab);
+}
+
+size_t core_workspace_bytes(const tk_ctx* ctx) {
+    int nsplit;
+    int64_t slab;
+    core_plan(ctx, nsplit, slab);
+    const int n = ctx->N - 1;
+    return (size_t)nsplit * ctx->ranks[n] * ctx->mode[n].K * 8;
+}
+
+int core_run(tk_ctx* ctx, const void* Y, const double* U, double* G, double* fit, hipStream_t s) {
+    const int n = ctx->N - 1;
+    const int64_t I = ctx->dims[n];
+    const int K = (int)ctx->mode[n].K;
+    const int R = ctx->ranks[n];
+    int nsplit;
+    int64_t slab;
+    core_plan(ctx, nsplit, slab);
+    double* part = ctx->ws.qrp;   // the QRP of the last mode has finished with its workspace
+    dim3 grid(cdiv(K, 256), (unsigned)nsplit, cdiv(R, 16));
+    if (ctx->dtype == TK_F64)
+        k_core_partial<double><<<grid, 256, 0, s>>>((const double*)Y, U, I, K, R, slab, part);
+    else
+        k_core_partial<float><<<grid, 256, 0, s>>>((const float*)Y, U, I, K, R, slab, part);
+    TK_LAUNCH_CHECK("k_core_partial");
+    k_core_finish<<<1, 1024, 0, s>>>(part, nsplit, K, R, ctx->normx2, G, fit);
+    TK_LAUNCH_CHECK("k_core_finish");
+    return TK_OK;
+}
+
+int reconstruct_run(tk_ctx* ctx, const double* G, const double* const* U, int64_t m,
+                    const int32_t* coords, double* out, hipStream_t s) {
+    if (m == 0) return TK_OK;
+    ReconArgs a{};
+    a.N = ctx->N;
+    a.size = 1;
+    for (int t = 0; t < ctx->N; ++t) {
+        a.U[t] = U[t];
+        a.R[t] = ctx->ranks[t];
+        a.size *= ctx->ranks[t];
+    }
+    k_reconstruct<<<cdiv(m, 128), 128, 0, s>>>(a, G, m, coords, out);
+    TK_LAUNCH_CHECK("k_reconstruct");
+    return TK_OK;
+}
+
+}  // namespace tk

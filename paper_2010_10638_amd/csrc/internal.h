@@ -1,0 +1,146 @@
+// Internal declarations shared by the library's translation units (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/sptucker.h"
+
+namespace tk {
+
+constexpr int kMaxOrder = TK_MAX_ORDER;
+constexpr int kMaxK = TK_MAX_KCOLS;
+constexpr int kPadR = 16;          // factor copies are padded to a multiple of 16 columns
+constexpr int kGramMaxR = 32;      // Gram/Cholesky QRP route handles R_n up to this
+
+// bf16 storage (upper half of an IEEE binary32)
+typedef uint16_t bf16_t;
+
+__host__ __device__ inline float bf16_to_f32(bf16_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __uint_as_float(((uint32_t)b) << 16);
+#else
+    uint32_t u = ((uint32_t)b) << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+#endif
+}
+
+// Round to nearest, ties to even (NaN kept quiet).
+__host__ __device__ inline bf16_t f32_to_bf16(float f) {
+    uint32_t u;
+#if defined(__HIP_DEVICE_COMPILE__)
+    u = __float_as_uint(f);
+#else
+    __builtin_memcpy(&u, &f, 4);
+#endif
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bf16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+
+inline int pad_rank(int R) { return (R + kPadR - 1) / kPadR * kPadR; }
+inline size_t dtype_size(int dt) { return dt == TK_F64 ? 8 : (dt == TK_F32 ? 4 : 2); }
+inline size_t ytype_size(int dt) { return dt == TK_F64 ? 8 : 4; }
+
+// Per-mode sorted layout and the chunk walk of the TTMc kernels.
+struct ModeLayout {
+    int64_t S = 0;                  // distinct i_n
+    int32_t* rows = nullptr;        // [S]      distinct i_n, ascending
+    int32_t* ptr = nullptr;         // [S + 1]  row pointers
+    int32_t* idx = nullptr;         // [(N-1) * nnz] other-mode indices, modes ascending, SoA
+    void* val = nullptr;            // [nnz] TTMc storage type
+    int64_t K = 0;                  // prod_{t != n} R_t
+    int others[kMaxOrder - 1];      // other modes, ascending
+    int fiber_slot = -1;            // position of the fiber mode in others (order >= 4), else -1
+    // chunk walk
+    int64_t nchunks = 0;
+    int32_t* chunk_ptr = nullptr;   // [nchunks + 1] first nonzero of each chunk
+    int32_t* chunk_row = nullptr;   // [nchunks] compressed row holding the chunk's first nonzero
+    int32_t* chunk_slot = nullptr;  // [nchunks] carry slot of a chunk that starts inside a row, else -1
+    int64_t ncarry = 0;             // number of carry slots
+    int64_t nsplit = 0;             // rows whose nonzeros span several chunks
+    int32_t* split = nullptr;       // [nsplit * 3]: compressed row, first slot, last slot
+    int32_t max_row_nnz = 0;
+    // QRP route for this mode
+    int qrp_route = 0;              // 0 = Gram/Cholesky, 1 = small Householder on Y, 2 = fat (Y Y^T)
+};
+
+struct Workspace {
+    void* y = nullptr;              // Y_(n) of the sweep, max_n I_n * K_n entries of the Y type
+    size_t y_bytes = 0;
+    void* carry = nullptr;          // carry rows of split rows, max_n ncarry * K_n
+    size_t carry_bytes = 0;
+    double* qrp = nullptr;          // QRP / core scratch (FP64)
+    size_t qrp_bytes = 0;
+    int32_t* qrp_int = nullptr;     // pivots, flags
+    size_t qrp_int_bytes = 0;
+    double* scal = nullptr;         // small device scalars (fit when the caller gives none)
+};
+
+}  // namespace tk
+
+struct tk_ctx {
+    int N = 0;
+    int dtype = TK_F64;
+    uint32_t flags = 0;
+    int64_t dims[tk::kMaxOrder] = {};
+    int32_t ranks[tk::kMaxOrder] = {};
+    int64_t nnz = 0;                 // distinct coordinates
+    double normx2 = 0.0;
+    tk::ModeLayout mode[tk::kMaxOrder];
+    void* Ulp[tk::kMaxOrder] = {};   // factor copies in TTMc precision, I_k x ldU[k]
+    int ldU[tk::kMaxOrder] = {};
+    tk::Workspace ws;
+    hipStream_t last_stream = nullptr;
+    int device = 0;
+    // region timing of hooi_sweep (tucker_profile)
+    hipEvent_t* prof_ev = nullptr;   // [capacity][2N + 2]
+    int prof_cap = 0;
+    int prof_used = 0;
+};
+
+namespace tk {
+
+int set_error(int code, const char* fmt, ...);
+int hip_error(hipError_t e, const char* what);
+
+#define TK_HIP(call)                                                  \
+    do {                                                              \
+        hipError_t e_ = (call);                                       \
+        if (e_ != hipSuccess) return ::tk::hip_error(e_, #call);      \
+    } while (0)
+
+#define TK_LAUNCH_CHECK(what)                                         \
+    do {                                                              \
+        hipError_t e_ = hipGetLastError();                            \
+        if (e_ != hipSuccess) return ::tk::hip_error(e_, what);       \
+    } while (0)
+
+// Layout builder (build.hip)
+int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t nnz_in,
+                 hipStream_t s);
+
+// Conversions (core.hip)
+int convert_factor(tk_ctx* ctx, int k, const double* U, hipStream_t s);
+int fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// TTMc (ttmc.hip): uses ctx->Ulp copies
+int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s);
+
+// QRP (qrp.hip): Y -> U (FP64) and the low-precision copy ctx->Ulp[mode]
+int qrp_run(tk_ctx* ctx, int mode, const void* Y, double* U, int32_t* piv, hipStream_t s);
+size_t qrp_workspace_bytes(const tk_ctx* ctx, int mode);
+int qrp_route(const tk_ctx* ctx, int mode);
+
+// Core, fit, reconstruct (core.hip)
+int core_run(tk_ctx* ctx, const void* Y, const double* U, double* G, double* fit, hipStream_t s);
+size_t core_workspace_bytes(const tk_ctx* ctx);
+int reconstruct_run(tk_ctx* ctx, const double* G, const double* const* U, int64_t m,
+                    const int32_t* coords, double* out, hipStream_t s);
+
+}  // namespace tk

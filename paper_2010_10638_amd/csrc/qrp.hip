@@ -1,0 +1,593 @@
+// U_n <- QRP(Y_(n), R_n) in FP64 (paper Alg. 2; Sec. III-D).
+//
+// Only the first R_n columns of Q are needed, and the first R_n pivot steps of a Householder QRP
+// depend only on the column norms of the partly reduced matrix.  Two routes compute them:
+//
+// Route 0 (tall Y, K_n <= 1024, R_n <= 32) - one pass over Y instead of R_n passes:
+//   1. C = Y^T Y in FP64 (v_mfma_f64_16x16x4; products of fp32 inputs are exact in FP64).
+//   2. Pivoted Cholesky of C, R_n steps.  The Schur-complement diagonal equals the squared norm
+//      of each trailing sub-column that the Householder QRP compares, so the pivot sequence is the
+//      QRP's; the first maximum is taken over the physically swapped order, as in the textbook
+//      algorithm.  R11 = the R_n x R_n leading block of the triangular factor.
+//   3. Q1 = Y[:, piv] R11^{-1}, re-orthogonalised once (Cholesky of Q1^T Q1).
+//   4. Householder signs: Q_house = Q1 S with s_j chosen, column by column, so that the LU
+//      elimination (without pivoting) of the top R_n x R_n block of Q1 S - I has pivots <= -1 -
+//      the reconstruction of Householder vectors from an orthonormal basis (Ballard et al.,
+//      "Reconstructing Householder vectors from tall-skinny QR", 2014).  With the reflector
+//      v = x + sgn(x_0) ||x|| e_1, the Householder Q satisfies exactly this condition.
+//   A Cholesky breakdown or a pivot below 1e-12 of the largest diagonal (rank deficiency) sets a
+//   device flag and the Householder kernel below runs instead, on the device, without a host sync.
+//
+// Route 1 (small Y, R_n > 32, K_n > 1024, or the fallback) - eager textbook Householder QRP in
+// one workgroup: exact trailing-norm recompute, first-maximum pivot, v = x + sgn(x_0)||x|| e_1.
+// Route 2 (fat Y, K_n > I_n) - the same kernel on Y Y^T (I_n x I_n), as Sec. III-D prescribes.
+#include "internal.h"
+
+namespace tk {
+
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <typename YT>
+__device__ inline double yld(const YT* Y, int64_t i) { return (double)Y[i]; }
+
+// ---- Route 0 -------------------------------------------------------------------------------
+
+// Partial C for one 64x64 block pair (bi <= bj) over one slab of rows.  Wave w computes the 16
+// rows bi*64+16w.. of the block, 4 MFMA tiles across bj's 64 columns.
+template <typename YT>
+__global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, int64_t m, int n,
+                                                      int nb, int64_t slab, double* __restrict__ part) {
+    // decode the upper-triangular block pair
+    int b = blockIdx.x, bi = 0;
+    while (b >= nb - bi) { b -= nb - bi; ++bi; }
+    const int bj = bi + b;
+    const int split = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kq = lane >> 4, c16 = lane & 15;
+    const int64_t r0 = (int64_t)split * slab;
+    const int64_t r1 = min(m, r0 + slab);
+    const int ca = bi * 64 + 16 * w + c16;
+    d4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = d4_t{0, 0, 0, 0};
+    for (int64_t r = r0; r < r1; r += 4) {
+        const int64_t row = r + kq;
+        const bool rv = row < r1;
+        const double a = (rv && ca < n) ? yld(Y, row * n + ca) : 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int cb = bj * 64 + 16 * t + c16;
+            const double bvl = (rv && cb < n) ? yld(Y, row * n + cb) : 0.0;
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bvl, acc[t], 0, 0, 0);
+        }
+    }
+    double* P = part + (int64_t)split * n * n;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = bi * 64 + 16 * w + 4 * kq + v;
+            const int j = bj * 64 + 16 * t + c16;
+            if (i < n && j < n) P[(int64_t)i * n + j] = acc[t][v];
+        }
+}
+
+__global__ void k_gram_reduce(const double* __restrict__ part, int nsplit, int n, double* __restrict__ C) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * n) return;
+    int i = (int)(e / n), j = (int)(e % n);
+    if ((i >> 6) > (j >> 6)) { int t = i; i = j; j = t; }
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n * n + (int64_t)i * n + j];
+    C[e] = s;
+}
+
+// Pivoted Cholesky of C (n <= 1024), R steps, one workgroup.
+__global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, int n, int R,
+                                                  double* __restrict__ L, double* __restrict__ R11,
+                                                  int32_t* __restrict__ pivw, int32_t* __restrict__ flag) {
+    __shared__ double d[1024];
+    __shared__ int perm[1024];
+    __shared__ double lrow[64];
+    __shared__ double rv[32];
+    __shared__ int rp[32];
+    __shared__ double dmax0;
+    const int tid = threadIdx.x;
+    if (tid < n) { d[tid] = C[(int64_t)tid * n + tid]; perm[tid] = tid; }
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    // largest initial diagonal (scale for the rank test)
+    {
+        double v = (tid < n) ? d[tid] : -1.0;
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+        if ((tid & 63) == 0) rv[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) {
+            double mx = rv[0];
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) mx = fmax(mx, rv[k]);
+            dmax0 = mx;
+        }
+        __syncthreads();
+    }
+    bool bad = false;
+    for (int j = 0; j < R; ++j) {
+        // first maximum of d over positions j..n-1 of the current order
+        double v = -1.0;
+        int p = n;
+        if (tid >= j && tid < n) { v = d[perm[tid]]; p = tid; }
+        for (int o = 32; o > 0; o >>= 1) {
+            double v2 = __shfl_xor(v, o);
+            int p2 = __shfl_xor(p, o);
+            if (v2 > v || (v2 == v && p2 < p)) { v = v2; p = p2; }
+        }
+        if ((tid & 63) == 0) { rv[tid >> 6] = v; rp[tid >> 6] = p; }
+        __syncthreads();
+        if (tid == 0) {
+            double bv = rv[0];
+            int bp = rp[0];
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k)
+                if (rv[k] > bv || (rv[k] == bv && rp[k] < bp)) { bv = rv[k]; bp = rp[k]; }
+            int t = perm[j]; perm[j] = perm[bp]; perm[bp] = t;
+        }
+        __syncthreads();
+        const int cs = perm[j];
+        const double djj = d[cs];
+        if (!(djj > 1e-12 * dmax0)) bad = true;
+        const double ljj = bad ? 1.0 : sqrt(djj);
+        if (tid < j) lrow[tid] = L[(int64_t)cs * R + tid];
+        if (tid == 0) L[(int64_t)cs * R + j] = ljj;
+        __syncthreads();
+        if (tid > j && tid < n) {
+            const int c = perm[tid];
+            double sacc = C[(int64_t)c * n + cs];
+            for (int i = 0; i < j; ++i) sacc -= L[(int64_t)c * R + i] * lrow[i];
+            const double l = sacc / ljj;
+            L[(int64_t)c * R + j] = l;
+            d[c] -= l * l;
+        }
+        __syncthreads();
+    }
+    if (tid < R) pivw[tid] = perm[tid];
+    for (int e = tid; e < R * R; e += blockDim.x) {
+        const int i = e / R, j = e % R;
+        R11[e] = (i <= j) ? L[(int64_t)perm[j] * R + i] : 0.0;
+    }
+    if (bad && tid == 0) *flag = 1;
+}
+
+// Q1 = Y[:, piv] R11^{-1} row by row (forward substitution), and the partial Gram Q1^T Q1 of
+// this block's rows.
+template <typename YT>
+__global__ __launch_bounds__(256) void k_q1_gram(const YT* __restrict__ Y, int64_t m, int n, int R,
+                                                 const int32_t* __restrict__ pivw,
+                                                 const double* __restrict__ R11,
+                                                 const int32_t* __restrict__ flag, int64_t rows_per_block,
+                                                 double* __restrict__ part2) {
+    if (*flag) return;
+    __shared__ double sR[32 * 32];
+    __shared__ int sp[32];
+    __shared__ double q[256][33];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < R * R; e += 256) sR[e] = R11[e];
+    if (tid < R) sp[tid] = pivw[tid];
+    __syncthreads();
+    double g[4] = {0, 0, 0, 0};
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(m, r0 + rows_per_block);
+    for (int64_t base = r0; base < r1; base += 256) {
+        const int64_t row = base + tid;
+        if (row < r1) {
+            for (int j = 0; j < R; ++j) {
+                double sacc = yld(Y, row * n + sp[j]);
+                for (int i = 0; i < j; ++i) sacc -= q[tid][i] * sR[i * R + j];
+                q[tid][j] = sacc / sR[j * R + j];
+            }
+        } else {
+            for (int j = 0; j < R; ++j) q[tid][j] = 0.0;
+        }
+        __syncthreads();
+        const int nr = (int)min<int64_t>(256, r1 - base);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int pr = tid + 256 * k;
+            if (pr < R * R) {
+                const int a = pr / R, b = pr % R;
+                double sacc = 0.0;
+                for (int rr = 0; rr < nr; ++rr) sacc += q[rr][a] * q[rr][b];
+                g[k] += sacc;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int pr = tid + 256 * k;
+        if (pr < R * R) part2[(int64_t)blockIdx.x * R * R + pr] = g[k];
+    }
+}
+
+// Sum the Gram partials, Cholesky them, fold in R11^{-1}, fix the Householder signs.
+// M = R11^{-1} R2^{-1} S  (so that U = Y[:, piv] M).  Single thread does the R x R algebra.
+template <typename YT>
+__global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, int n, int R,
+                                                    const int32_t* __restrict__ pivw,
+                                                    const double* __restrict__ R11,
+                                                    const double* __restrict__ part2, int nblk,
+                                                    int32_t* __restrict__ flag, double* __restrict__ Mout,
+                                                    int32_t* __restrict__ piv_out) {
+    if (*flag) return;
+    __shared__ double G2[32 * 32];
+    __shared__ double A[32 * 32];
+    __shared__ double B[32 * 32];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < R * R; e += 256) {
+        double sacc = 0.0;
+        for (int k = 0; k < nblk; ++k) sacc += part2[(int64_t)k * R * R + e];
+        G2[e] = sacc;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    // Cholesky G2 = R2^T R2 (upper R2 stored in A)
+    for (int i = 0; i < R * R; ++i) A[i] = 0.0;
+    for (int j = 0; j < R; ++j) {
+        double djj = G2[j * R + j];
+        for (int k = 0; k < j; ++k) djj -= A[k * R + j] * A[k * R + j];
+        if (!(djj > 0.0)) { *flag = 1; return; }
+        const double rjj = sqrt(djj);
+        A[j * R + j] = rjj;
+        for (int c = j + 1; c < R; ++c) {
+            double sacc = G2[j * R + c];
+            for (int k = 0; k < j; ++k) sacc -= A[k * R + j] * A[k * R + c];
+            A[j * R + c] = sacc / rjj;
+        }
+    }
+    // B = R11^{-1} (upper), then G2 <- B * R2^{-1} = M'
+    for (int i = 0; i < R * R; ++i) B[i] = 0.0;
+    for (int c = 0; c < R; ++c) {          // solve R11 x = e_c (upper)
+        for (int i = R - 1; i >= 0; --i) {
+            double sacc = (i == c) ? 1.0 : 0.0;
+            for (int k = i + 1; k < R; ++k) sacc -= R11[i * R + k] * B[k * R + c];
+            B[i * R + c] = sacc / R11[i * R + i];
+        }
+    }
+    // M' = B R2^{-1}: solve M' R2 = B row by row (forward over columns)
+    for (int i = 0; i < R; ++i)
+        for (int c = 0; c < R; ++c) {
+            double sacc = B[i * R + c];
+            for (int k = 0; k < c; ++k) sacc -= G2[i * R + k] * A[k * R + c];
+            G2[i * R + c] = sacc / A[c * R + c];
+        }
+    // T = top R x R block of Q1' = Y[0:R, piv] M'
+    for (int i = 0; i < R; ++i)
+        for (int c = 0; c < R; ++c) {
+            double sacc = 0.0;
+            for (int k = 0; k < R; ++k) sacc += yld(Y, (int64_t)i * n + pivw[k]) * G2[k * R + c];
+            B[i * R + c] = sacc;
+        }
+    // sign rule: LU of (T S - I) without pivoting, choosing s_j so that the pivot is <= -1
+    double* sgn = A;  // R2 is no longer needed
+    for (int j = 0; j < R; ++j) {
+        const double pv = B[j * R + j];
+        const double sj = (pv >= 0.0) ? -1.0 : 1.0;
+        sgn[j] = sj;
+        for (int i = 0; i < R; ++i) B[i * R + j] *= sj;
+        B[j * R + j] -= 1.0;
+        const double piv = B[j * R + j];
+        for (int i = j + 1; i < R; ++i) {
+            const double l = B[i * R + j] / piv;
+            for (int c = j + 1; c < R; ++c) B[i * R + c] -= l * B[j * R + c];
+            B[i * R + j] = l;
+        }
+    }
+    for (int k = 0; k < R; ++k)
+        for (int c = 0; c < R; ++c) Mout[k * R + c] = G2[k * R + c] * sgn[c];
+    if (piv_out)
+        for (int j = 0; j < R; ++j) piv_out[j] = pivw[j];
+}
+
+template <typename YT, typename LT>
+__global__ __launch_bounds__(256) void k_form_u(const YT* __restrict__ Y, int64_t m, int n, int R,
+                                                const int32_t* __restrict__ pivw,
+                                                const double* __restrict__ M,
+                                                const int32_t* __restrict__ flag,
+                                                double* __restrict__ U, LT* __restrict__ Ulp, int ldlp) {
+    if (*flag) return;
+    __shared__ double sM[32 * 32];
+    __shared__ int sp[32];
+    for (int e = threadIdx.x; e < R * R; e += 256) sM[e] = M[e];
+    if (threadIdx.x < R) sp[threadIdx.x] = pivw[threadIdx.x];
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= m) return;
+    double b[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) b[j] = (j < R) ? yld(Y, row * n + sp[j]) : 0.0;
+    for (int c = 0; c < R; ++c) {
+        double u = 0.0;
+#pragma unroll
+        for (int j = 0; j < 32; ++j)
+            if (j < R) u += b[j] * sM[j * R + c];
+        U[row * R + c] = u;
+        if constexpr (sizeof(LT) == 8) Ulp[row * ldlp + c] = u;
+        else if constexpr (sizeof(LT) == 4) Ulp[row * ldlp + c] = (float)u;
+        else Ulp[row * ldlp + c] = f32_to_bf16((float)u);
+    }
+    for (int c = R; c < ldlp; ++c) Ulp[row * ldlp + c] = LT(0);
+}
+
+// ---- Routes 1 and 2 ------------------------------------------------------------------------
+
+// A (m x n FP64, row-major) <- Y (gated: runs only when *gate == gate_val, gate may be NULL).
+template <typename YT>
+__global__ void k_copy_f64(const YT* __restrict__ Y, int64_t total, double* __restrict__ A,
+                           const int32_t* __restrict__ gate, int gate_val) {
+    if (gate && *gate != gate_val) return;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x)
+        A[e] = yld(Y, e);
+}
+
+// A = Y Y^T (I x I), FP64 accumulation.
+template <typename YT>
+__global__ void k_syrk_rows(const YT* __restrict__ Y, int I, int K, double* __restrict__ A) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)I * I) return;
+    const int a = (int)(e / I), b = (int)(e % I);
+    double s = 0.0;
+    for (int c = 0; c < K; ++c) s += yld(Y, (int64_t)a * K + c) * yld(Y, (int64_t)b * K + c);
+    A[e] = s;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+    return s;
+}
+
+// Eager Householder QRP on A (m x n, FP64, in place), R steps, one workgroup of 1024 threads,
+// then Q[:, :R] = H_0 ... H_{R-1} [I; 0] into U (m x R) and the low-precision copy.
+template <typename LT>
+__global__ __launch_bounds__(1024) void k_house_qrp(double* __restrict__ A, int64_t m, int n, int R,
+                                                    double* __restrict__ V, double* __restrict__ w,
+                                                    double* __restrict__ beta_s, int32_t* __restrict__ perm,
+                                                    const int32_t* __restrict__ gate, int gate_val,
+                                                    double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
+                                                    int32_t* __restrict__ piv_out) {
+    if (gate && *gate != gate_val) return;
+    __shared__ double red[16];
+    __shared__ double rv[16];
+    __shared__ int rp[16];
+    __shared__ int pbest;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int c = tid; c < n; c += nt) perm[c] = c;
+    __syncthreads();
+    for (int j = 0; j < R; ++j) {
+        // trailing norms, exact recompute; first maximum
+        double bv = -1.0;
+        int bp = n;
+        for (int c = j + tid; c < n; c += nt) {
+            double s = 0.0;
+            for (int64_t i = j; i < m; ++i) s += A[i * n + c] * A[i * n + c];
+            if (s > bv) { bv = s; bp = c; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            double v2 = __shfl_xor(bv, o);
+            int p2 = __shfl_xor(bp, o);
+            if (v2 > bv || (v2 == bv && p2 < bp)) { bv = v2; bp = p2; }
+        }
+        if ((tid & 63) == 0) { rv[tid >> 6] = bv; rp[tid >> 6] = bp; }
+        __syncthreads();
+        if (tid == 0) {
+            double b0 = rv[0];
+            int p0 = rp[0];
+            for (int k = 1; k < nt / 64; ++k)
+                if (rv[k] > b0 || (rv[k] == b0 && rp[k] < p0)) { b0 = rv[k]; p0 = rp[k]; }
+            pbest = p0;
+            int t = perm[j]; perm[j] = perm[p0]; perm[p0] = t;
+        }
+        __syncthreads();
+        const int p = pbest;
+        if (p != j)
+            for (int64_t i = tid; i < m; i += nt) {
+                double t = A[i * n + j]; A[i * n + j] = A[i * n + p]; A[i * n + p] = t;
+            }
+        __syncthreads();
+        double part = 0.0;
+        for (int64_t i = j + tid; i < m; i += nt) part += A[i * n + j] * A[i * n + j];
+        const double alpha = sqrt(block_sum(part, red));
+        if (alpha == 0.0) {
+            if (tid == 0) beta_s[j] = 0.0;
+            for (int64_t i = tid; i < m; i += nt) V[i * R + j] = 0.0;
+            __syncthreads();
+            continue;
+        }
+        const double x0 = A[(int64_t)j * n + j];
+        part = 0.0;
+        for (int64_t i = tid; i < m; i += nt) {
+            double v = 0.0;
+            if (i >= j) {
+                v = A[i * n + j];
+                if (i == j) v += (x0 >= 0.0 ? 1.0 : -1.0) * alpha;
+            }
+            V[i * R + j] = v;
+            part += v * v;
+        }
+        const double vv = block_sum(part, red);
+        const double beta = 2.0 / vv;
+        if (tid == 0) beta_s[j] = beta;
+        __syncthreads();
+        for (int c = j + tid; c < n; c += nt) {
+            double s = 0.0;
+            for (int64_t i = j; i < m; ++i) s += V[i * R + j] * A[i * n + c];
+            w[c] = beta * s;
+        }
+        __syncthreads();
+        const int64_t cols = n - j;
+        for (int64_t e = tid; e < (m - j) * cols; e += nt) {
+            const int64_t i = j + e / cols;
+            const int c = j + (int)(e % cols);
+            A[i * n + c] -= V[i * R + j] * w[c];
+        }
+        __syncthreads();
+    }
+    // Q = H_0 ... H_{R-1} [I; 0]
+    for (int64_t e = tid; e < m * R; e += nt) U[e] = ((e / R) == (e % R)) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int j = R - 1; j >= 0; --j) {
+        const double beta = beta_s[j];
+        if (beta == 0.0) continue;
+        for (int c = tid; c < R; c += nt) {
+            double s = 0.0;
+            for (int64_t i = j; i < m; ++i) s += V[i * R + j] * U[i * R + c];
+            w[c] = beta * s;
+        }
+        __syncthreads();
+        for (int64_t e = tid; e < (m - j) * R; e += nt) {
+            const int64_t i = j + e / R;
+            const int c = (int)(e % R);
+            U[i * R + c] -= V[i * R + j] * w[c];
+        }
+        __syncthreads();
+    }
+    for (int64_t e = tid; e < m * ldlp; e += nt) {
+        const int64_t i = e / ldlp;
+        const int c = (int)(e % ldlp);
+        const double u = (c < R) ? U[i * R + c] : 0.0;
+        if constexpr (sizeof(LT) == 8) Ulp[e] = u;
+        else if constexpr (sizeof(LT) == 4) Ulp[e] = (float)u;
+        else Ulp[e] = f32_to_bf16((float)u);
+    }
+    if (piv_out && tid < R) piv_out[tid] = perm[tid];
+}
+
+struct QrpPlan {
+    int route;
+    int64_t m;       // rows of the QRP input
+    int n;           // columns of the QRP input
+    int R;
+    int nb;          // 64-column blocks (route 0)
+    int nsplit;      // row slabs of the Gram (route 0)
+    int64_t slab;
+    int nblk2;       // blocks of the Q1 Gram (route 0)
+    int64_t rows2;
+    // offsets into the FP64 workspace (in doubles)
+    int64_t o_part, o_C, o_L, o_R11, o_part2, o_M, o_A, o_V, o_w, o_beta;
+    int64_t total;
+};
+
+QrpPlan plan(const tk_ctx* ctx, int mode) {
+    QrpPlan p{};
+    const int64_t I = ctx->dims[mode];
+    const int64_t K = ctx->mode[mode].K;
+    const int R = ctx->ranks[mode];
+    const bool fat = K > I;
+    p.R = R;
+    if (fat && !(ctx->flags & TK_FLAG_NO_FAT_RULE)) {
+        p.route = 2;
+        p.m = I;
+        p.n = (int)I;
+    } else {
+        p.m = I;
+        p.n = (int)K;
+        p.route = (fat || R > kGramMaxR || K > 1024 || I * K <= 65536) ? 1 : 0;
+    }
+    int64_t off = 0;
+    if (p.route == 0) {
+        p.nb = (p.n + 63) / 64;
+        const int64_t nn = (int64_t)p.n * p.n;
+        int64_t cap = std::max<int64_t>(1, (int64_t)(32u << 20) / 8 / nn);  // <= 32 MB of partials
+        p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(p.m + 511) / 512, 128, cap}));
+        p.slab = ((p.m + p.nsplit - 1) / p.nsplit + 3) / 4 * 4;
+        p.nsplit = (int)((p.m + p.slab - 1) / p.slab);
+        p.rows2 = std::max<int64_t>(256, (p.m + 511) / 512);
+        p.rows2 = (p.rows2 + 255) / 256 * 256;
+        p.nblk2 = (int)((p.m + p.rows2 - 1) / p.rows2);
+        p.o_part = off; off += (int64_t)p.nsplit * nn;
+        p.o_C = off; off += nn;
+        p.o_L = off; off += (int64_t)p.n * R;
+        p.o_R11 = off; off += (int64_t)R * R;
+        p.o_part2 = off; off += (int64_t)p.nblk2 * R * R;
+        p.o_M = off; off += (int64_t)R * R;
+    }
+    // Householder workspace (route 1/2, and the route-0 fallback on Y)
+    const int64_t hm = (p.route == 0) ? I : p.m;
+    const int64_t hn = (p.route == 0) ? K : p.n;
+    p.o_A = off; off += hm * hn;
+    p.o_V = off; off += hm * R;
+    p.o_w = off; off += std::max<int64_t>(hn, R);
+    p.o_beta = off; off += R;
+    p.total = off;
+    return p;
+}
+
+template <typename YT, typename LT>
+int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipStream_t s) {
+    const QrpPlan p = plan(ctx, mode);
+    double* W = ctx->ws.qrp;
+    int32_t* flag = ctx->ws.qrp_int;            // [0] flag
+    int32_t* pivw = ctx->ws.qrp_int + 16;       // [16 .. 16+R)
+    int32_t* perm = ctx->ws.qrp_int + 64;       // Householder permutation, n entries
+    LT* Ulp = (LT*)ctx->Ulp[mode];
+    const int ldlp = ctx->ldU[mode];
+    const int64_t I = ctx->dims[mode];
+    const int64_t K = ctx->mode[mode].K;
+    if (p.route == 0) {
+        dim3 g1((unsigned)(p.nb * (p.nb + 1) / 2), (unsigned)p.nsplit);
+        k_gram_partial<YT><<<g1, 256, 0, s>>>(Y, p.m, p.n, p.nb, p.slab, W + p.o_part);
+        TK_LAUNCH_CHECK("k_gram_partial");
+        k_gram_reduce<<<cdiv((int64_t)p.n * p.n, 256), 256, 0, s>>>(W + p.o_part, p.nsplit, p.n, W + p.o_C);
+        TK_LAUNCH_CHECK("k_gram_reduce");
+        k_pivchol<<<1, 1024, 0, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, W + p.o_R11, pivw, flag);
+        TK_LAUNCH_CHECK("k_pivchol");
+        k_q1_gram<YT><<<(unsigned)p.nblk2, 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_R11, flag, p.rows2,
+                                                         W + p.o_part2);
+        TK_LAUNCH_CHECK("k_q1_gram");
+        k_qrp_finish<YT><<<1, 256, 0, s>>>(Y, p.n, p.R, pivw, W + p.o_R11, W + p.o_part2, p.nblk2, flag,
+                                           W + p.o_M, piv);
+        TK_LAUNCH_CHECK("k_qrp_finish");
+        k_form_u<YT, LT><<<cdiv(p.m, 256), 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_M, flag, U, Ulp, ldlp);
+        TK_LAUNCH_CHECK("k_form_u");
+        // fallback, gated on the flag
+        k_copy_f64<YT><<<1024, 256, 0, s>>>(Y, I * K, W + p.o_A, flag, 1);
+        TK_LAUNCH_CHECK("k_copy_f64");
+        k_house_qrp<LT><<<1, 1024, 0, s>>>(W + p.o_A, I, (int)K, p.R, W + p.o_V, W + p.o_w, W + p.o_beta, perm, flag, 1, U,
+                                           Ulp, ldlp, piv);
+        TK_LAUNCH_CHECK("k_house_qrp");
+        return TK_OK;
+    }
+    if (p.route == 2) {
+        k_syrk_rows<YT><<<cdiv(I * I, 256), 256, 0, s>>>(Y, (int)I, (int)K, W + p.o_A);
+        TK_LAUNCH_CHECK("k_syrk_rows");
+    } else {
+        k_copy_f64<YT><<<1024, 256, 0, s>>>(Y, I * K, W + p.o_A, nullptr, 0);
+        TK_LAUNCH_CHECK("k_copy_f64");
+    }
+    k_house_qrp<LT><<<1, 1024, 0, s>>>(W + p.o_A, p.m, p.n, p.R, W + p.o_V, W + p.o_w, W + p.o_beta, perm, nullptr, 0, U,
+                                       Ulp, ldlp, piv);
+    TK_LAUNCH_CHECK("k_house_qrp");
+    return TK_OK;
+}
+
+}  // namespace
+
+size_t qrp_workspace_bytes(const tk_ctx* ctx, int mode) { return (size_t)plan(ctx, mode).total * 8; }
+
+int qrp_route(const tk_ctx* ctx, int mode) { return plan(ctx, mode).route; }
+
+int qrp_run(tk_ctx* ctx, int mode, const void* Y, double* U, int32_t* piv, hipStream_t s) {
+    switch (ctx->dtype) {
+        case TK_F64: return run_typed<double, double>(ctx, mode, (const double*)Y, U, piv, s);
+        case TK_F32: return run_typed<float, float>(ctx, mode, (const float*)Y, U, piv, s);
+        default: return run_typed<float, bf16_t>(ctx, mode, (const float*)Y, U, piv, s);
+    }
+}
+
+}  // namespace tk

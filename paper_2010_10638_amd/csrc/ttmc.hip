@@ -1,0 +1,273 @@
+// Sparse TTMc, Y_(n)(i_n, :) += x * kron_{t != n} U_t(i_t, :)   (paper Alg. 2; Sec. III-C).
+//
+// The nonzeros of mode n are stored sorted by row (i_n) and cut into chunks of whole rows (a row
+// longer than the chunk target is cut into pieces).  One wavefront walks one chunk: for each row
+// segment it accumulates the Kronecker rows of its nonzeros in registers (same-row reduction
+// before any global write, the accumulation over shared indices of Sec. III-C), then stores the
+// finished row once.  The wave that holds the first nonzero of a row owns it and also writes the
+// zero rows in the gap before it; pieces of a split row write their partial sums to a carry slot
+// and a fix-up pass adds the slots in order, so the result is deterministic and Y needs no
+// separate zero-fill.
+//
+// Kernels:
+//   k_ttmc3_mfma  - order 3 with R_a, R_b <= 16.  The row sum  sum_p (x_p a_p) b_p^T  is a
+//                   rank-k product over the row's nonzeros, computed 4 nonzeros at a time by
+//                   v_mfma_{f32,f64}_16x16x4: lane l carries nonzero l/16 and factor column l%16.
+//   k_ttmc_generic- any order 2..8 and K_n <= 4096 on the vector ALU; lane l owns columns l+64j.
+#include "internal.h"
+
+namespace tk {
+
+namespace {
+
+struct TtmcArgs {
+    const int32_t* chunk_ptr;
+    const int32_t* chunk_row;
+    const int32_t* chunk_slot;
+    int32_t nchunks;
+    const int32_t* ptr;
+    const int32_t* rows;
+    int32_t S;
+    int32_t In;
+    const int32_t* idx;       // [nm1][nnz]
+    int64_t nnz;
+    const void* val;
+    const void* F[kMaxOrder - 1];
+    int32_t ld[kMaxOrder - 1];
+    int32_t R[kMaxOrder - 1];
+    int32_t nm1;
+    int32_t K;
+    void* Y;
+    void* carry;
+};
+
+template <typename T> __device__ inline T ld_cvt(const void* p, int64_t i);
+template <> __device__ inline double ld_cvt<double>(const void* p, int64_t i) { return ((const double*)p)[i]; }
+template <typename ST> __device__ inline float ld_f32(const void* p, int64_t i);
+template <> __device__ inline float ld_f32<float>(const void* p, int64_t i) { return ((const float*)p)[i]; }
+template <> __device__ inline float ld_f32<bf16_t>(const void* p, int64_t i) { return bf16_to_f32(((const bf16_t*)p)[i]); }
+
+template <typename AT, typename ST>
+__device__ inline AT load_as(const void* p, int64_t i) {
+    if constexpr (sizeof(AT) == 8) return ((const double*)p)[i];
+    else return ld_f32<ST>(p, i);
+}
+
+// Zero the rows of Y strictly between the previous non-empty row and row s (and, for the last
+// non-empty row, every row after it).  Called by the owner of row s, once per row.
+template <typename AT>
+__device__ inline void zero_gaps(const TtmcArgs& a, int s, int lane) {
+    AT* Y = (AT*)a.Y;
+    int g0 = (s == 0) ? 0 : a.rows[s - 1] + 1;
+    int g1 = a.rows[s];
+    int64_t K = a.K;
+    for (int64_t e = (int64_t)g0 * K + lane; e < (int64_t)g1 * K; e += 64) Y[e] = AT(0);
+    if (s == a.S - 1)
+        for (int64_t e = (int64_t)(g1 + 1) * K + lane; e < (int64_t)a.In * K; e += 64) Y[e] = AT(0);
+}
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+template <typename AT> struct Acc;
+template <> struct Acc<float> {
+    typedef f4_t type;
+    static __device__ inline f4_t mfma(float a, float b, f4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Acc<double> {
+    typedef d4_t type;
+    static __device__ inline d4_t mfma(double a, double b, d4_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename AT, typename ST>
+__global__ __launch_bounds__(256) void k_ttmc3_mfma(TtmcArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int ch = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ch >= a.nchunks) return;
+    const int kq = lane >> 4;         // which of the 4 nonzeros of a step this lane carries
+    const int m = lane & 15;          // factor column carried by this lane
+    const int q0 = a.chunk_ptr[ch], q1 = a.chunk_ptr[ch + 1];
+    const int slot = a.chunk_slot[ch];
+    const int32_t* __restrict__ ia = a.idx;
+    const int32_t* __restrict__ ib = a.idx + a.nnz;
+    const int Ra = a.R[0], Rb = a.R[1], K = a.K;
+    int s = a.chunk_row[ch];
+    int q = q0;
+    while (q < q1) {
+        const int rs = a.ptr[s];
+        const int end = min(a.ptr[s + 1], q1);
+        const bool owner = rs >= q0;
+        typename Acc<AT>::type acc = {0, 0, 0, 0};
+        for (int p = q; p < end; p += 4) {
+            const int qq = p + kq;
+            const bool valid = qq < end;
+            const int qc = valid ? qq : end - 1;
+            const AT x = valid ? load_as<AT, ST>(a.val, qc) : AT(0);
+            const AT av = load_as<AT, ST>(a.F[0], (int64_t)ia[qc] * 16 + m) * x;
+            const AT bv = load_as<AT, ST>(a.F[1], (int64_t)ib[qc] * 16 + m);
+            acc = Acc<AT>::mfma(av, bv, acc);
+        }
+        AT* dst = owner ? (AT*)a.Y + (int64_t)a.rows[s] * K : (AT*)a.carry + (int64_t)slot * K;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 4 * kq + v;
+            if (r < Ra && m < Rb) dst[r * Rb + m] = acc[v];
+        }
+        if (owner) zero_gaps<AT>(a, s, lane);
+        q = end;
+        ++s;
+    }
+}
+
+template <typename AT, typename ST, int KPL>
+__global__ __launch_bounds__(256) void k_ttmc_generic(TtmcArgs a) {
+    extern __shared__ uint16_t dig[];  // [K][nm1]: digit of each other mode for column c
+    for (int c = threadIdx.x; c < a.K; c += blockDim.x) {
+        int rem = c;
+        for (int j = a.nm1 - 1; j >= 0; --j) {
+            dig[c * a.nm1 + j] = (uint16_t)(rem % a.R[j]);
+            rem /= a.R[j];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int ch = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ch >= a.nchunks) return;
+    const int q0 = a.chunk_ptr[ch], q1 = a.chunk_ptr[ch + 1];
+    const int slot = a.chunk_slot[ch];
+    const int K = a.K, nm1 = a.nm1;
+    int s = a.chunk_row[ch];
+    int q = q0;
+    while (q < q1) {
+        const int rs = a.ptr[s];
+        const int end = min(a.ptr[s + 1], q1);
+        const bool owner = rs >= q0;
+        AT acc[KPL];
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) acc[j] = AT(0);
+        for (int p = q; p < end; ++p) {
+            const AT x = load_as<AT, ST>(a.val, p);
+            int64_t base[kMaxOrder - 1];
+#pragma unroll
+            for (int t = 0; t < kMaxOrder - 1; ++t)
+                base[t] = (t < nm1) ? (int64_t)a.idx[(int64_t)t * a.nnz + p] * a.ld[t] : 0;
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                const int c = lane + 64 * j;
+                if (c < K) {
+                    AT v = x;
+#pragma unroll
+                    for (int t = 0; t < kMaxOrder - 1; ++t)
+                        if (t < nm1) v *= load_as<AT, ST>(a.F[t], base[t] + dig[c * nm1 + t]);
+                    acc[j] += v;
+                }
+            }
+        }
+        AT* dst = owner ? (AT*)a.Y + (int64_t)a.rows[s] * K : (AT*)a.carry + (int64_t)slot * K;
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+            const int c = lane + 64 * j;
+            if (c < K) dst[c] = acc[j];
+        }
+        if (owner) zero_gaps<AT>(a, s, lane);
+        q = end;
+        ++s;
+    }
+}
+
+// Adds the carry slots of each split row, in slot order, to the row written by its owner.
+template <typename AT>
+__global__ __launch_bounds__(256) void k_ttmc_fixup(const int32_t* __restrict__ split,
+                                                    const int32_t* __restrict__ rows, int K,
+                                                    const AT* __restrict__ carry, AT* __restrict__ Y) {
+    const int sp = blockIdx.x;
+    const int s = split[3 * sp], f = split[3 * sp + 1], l = split[3 * sp + 2];
+    AT* y = Y + (int64_t)rows[s] * K;
+    for (int c = threadIdx.x; c < K; c += blockDim.x) {
+        AT acc = AT(0);
+        for (int k = f; k <= l; ++k) acc += carry[(int64_t)k * K + c];
+        y[c] += acc;
+    }
+}
+
+template <typename AT, typename ST>
+int launch_generic(const TtmcArgs& a, hipStream_t s) {
+    unsigned grid = (unsigned)((a.nchunks + 3) / 4);
+    size_t lds = (size_t)a.K * a.nm1 * sizeof(uint16_t);
+    int kpl = (a.K + 63) / 64;
+#define TK_GEN(KP)                                                                      \
+    k_ttmc_generic<AT, ST, KP><<<grid, 256, lds, s>>>(a);                               \
+    TK_LAUNCH_CHECK("k_ttmc_generic");                                                  \
+    return TK_OK;
+    if (kpl <= 1) { TK_GEN(1) }
+    if (kpl <= 2) { TK_GEN(2) }
+    if (kpl <= 4) { TK_GEN(4) }
+    if (kpl <= 8) { TK_GEN(8) }
+    if (kpl <= 16) { TK_GEN(16) }
+    if (kpl <= 32) { TK_GEN(32) }
+    TK_GEN(64)
+#undef TK_GEN
+}
+
+}  // namespace
+
+int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s) {
+    const ModeLayout& ml = ctx->mode[mode];
+    const int N = ctx->N;
+    const int64_t In = ctx->dims[mode];
+    const size_t ysz = ytype_size(ctx->dtype);
+    if (ml.nchunks == 0) return fill_zero(Y, (size_t)In * ml.K * ysz, s);
+    TtmcArgs a{};
+    a.chunk_ptr = ml.chunk_ptr;
+    a.chunk_row = ml.chunk_row;
+    a.chunk_slot = ml.chunk_slot;
+    a.nchunks = (int32_t)ml.nchunks;
+    a.ptr = ml.ptr;
+    a.rows = ml.rows;
+    a.S = (int32_t)ml.S;
+    a.In = (int32_t)In;
+    a.idx = ml.idx;
+    a.nnz = ctx->nnz;
+    a.val = ml.val;
+    a.nm1 = N - 1;
+    a.K = (int32_t)ml.K;
+    a.Y = Y;
+    a.carry = ctx->ws.carry;
+    bool mfma_ok = (N == 3);
+    for (int j = 0; j < N - 1; ++j) {
+        int t = ml.others[j];
+        a.F[j] = ctx->Ulp[t];
+        a.ld[j] = ctx->ldU[t];
+        a.R[j] = ctx->ranks[t];
+        mfma_ok = mfma_ok && a.R[j] <= 16 && a.ld[j] == 16;
+    }
+    const unsigned grid = (unsigned)((ml.nchunks + 3) / 4);
+    int st = TK_OK;
+    if (mfma_ok) {
+        if (ctx->dtype == TK_F64) k_ttmc3_mfma<double, double><<<grid, 256, 0, s>>>(a);
+        else if (ctx->dtype == TK_F32) k_ttmc3_mfma<float, float><<<grid, 256, 0, s>>>(a);
+        else k_ttmc3_mfma<float, bf16_t><<<grid, 256, 0, s>>>(a);
+        TK_LAUNCH_CHECK("k_ttmc3_mfma");
+    } else {
+        if (ctx->dtype == TK_F64) st = launch_generic<double, double>(a, s);
+        else if (ctx->dtype == TK_F32) st = launch_generic<float, float>(a, s);
+        else st = launch_generic<float, bf16_t>(a, s);
+        if (st) return st;
+    }
+    if (ml.nsplit > 0) {
+        if (ctx->dtype == TK_F64)
+            k_ttmc_fixup<double><<<(unsigned)ml.nsplit, 256, 0, s>>>(ml.split, ml.rows, (int)ml.K,
+                                                                     (const double*)ctx->ws.carry, (double*)Y);
+        else
+            k_ttmc_fixup<float><<<(unsigned)ml.nsplit, 256, 0, s>>>(ml.split, ml.rows, (int)ml.K,
+                                                                    (const float*)ctx->ws.carry, (float*)Y);
+        TK_LAUNCH_CHECK("k_ttmc_fixup");
+    }
+    return TK_OK;
+}
+
+}  // namespace tk

@@ -1,0 +1,291 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle, on seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import bf16_round, cast_inputs, cast_vals, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+TOL_Y = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def tk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_10638_amd as tk_mod
+    tk_mod.load_library()
+    return tk_mod
+
+
+def to_dev(coords, vals):
+    return (torch.from_numpy(np.ascontiguousarray(coords, dtype=np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(vals, dtype=np.float64)).cuda())
+
+
+def dev_list(U):
+    return [torch.from_numpy(np.ascontiguousarray(u, dtype=np.float64)).cuda() for u in U]
+
+
+def make(tk, w, dtype, fat_rule=True):
+    c, v = to_dev(w.coords, w.vals)
+    return tk.tucker_init(c, v, w.dims, w.ranks, dtype=dtype, fat_rule=fat_rule)
+
+
+def with_duplicates(w, k=37, seed=0):
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(w.nnz, size=min(k, w.nnz), replace=False)
+    c = np.concatenate([w.coords, w.coords[:, pick]], axis=1)
+    v = np.concatenate([w.vals, rng.standard_normal(pick.size)])
+    perm = rng.permutation(c.shape[1])
+    return c[:, perm], v[perm]
+
+
+# ------------------------------------------------------------------------------------------
+# Layout (bit-exact)
+# ------------------------------------------------------------------------------------------
+
+def check_csf(tk, ctx, coords, vals, dtype):
+    cc, cv = oracle.coalesce(coords, vals, ctx.dims)
+    info = tk.tucker_get_info(ctx)
+    assert info["nnz"] == cv.size
+    for mode in range(ctx.order):
+        exp = oracle.csf(cc, cv, mode)
+        got = tk.tucker_get_csf(ctx, mode)
+        assert info["rows"][mode] == exp["rows"].size
+        np.testing.assert_array_equal(got["rows"].cpu().numpy(), exp["rows"])
+        np.testing.assert_array_equal(got["ptr"].cpu().numpy(), exp["ptr"])
+        np.testing.assert_array_equal(got["idx"].cpu().numpy(), exp["idx"])
+        gv = got["vals"].cpu().numpy()
+        if dtype == "f64":
+            np.testing.assert_array_equal(gv, exp["vals"])
+        elif dtype == "f32":
+            np.testing.assert_array_equal(gv, exp["vals"].astype(np.float32))
+        else:
+            np.testing.assert_array_equal(gv, bf16_round(exp["vals"]))
+    assert abs(info["normx2"] - float(cv @ cv)) <= 1e-12 * max(1.0, float(cv @ cv))
+
+
+def test_csf_table1(tk):
+    lines = [l.split() for l in open("tests/golden/table1_coo.txt") if l.strip() and not l.startswith("#")]
+    arr = np.array([[float(x) for x in r] for r in lines])
+    coords = (arr[:, :4].T - 1).astype(np.int32)
+    vals = arr[:, 4]
+    c, v = to_dev(coords, vals)
+    ctx = tk.tucker_init(c, v, [5, 5, 5, 5], [1, 1, 1, 1], dtype="f64")
+    check_csf(tk, ctx, coords, vals, "f64")
+    got = tk.tucker_get_csf(ctx, 3)
+    assert got["rows"].cpu().tolist() == [0, 3, 4]
+    assert got["ptr"].cpu().tolist() == [0, 1, 2, 4]
+    assert got["vals"].cpu().tolist() == [2.0, 5.0, 7.5, 4.0]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("dims", [[40, 300, 200], [30, 20, 25, 12]])
+def test_csf_bit_exact_with_duplicates(tk, dtype, dims):
+    w = synth.small_uniform(5, dims, [2] * len(dims), 6000)
+    coords, vals = with_duplicates(w)
+    c, v = to_dev(coords, vals)
+    ctx = tk.tucker_init(c, v, dims, [2] * len(dims), dtype=dtype)
+    check_csf(tk, ctx, coords, vals, dtype)
+    # determinism: a second build gives identical bits
+    ctx2 = tk.tucker_init(c, v, dims, [2] * len(dims), dtype=dtype)
+    for mode in range(len(dims)):
+        a, b = tk.tucker_get_csf(ctx, mode), tk.tucker_get_csf(ctx2, mode)
+        for k in a:
+            assert torch.equal(a[k], b[k])
+
+
+def test_range_error(tk):
+    coords = np.array([[0, 1], [0, 7]], dtype=np.int32)
+    c, v = to_dev(coords, np.ones(2))
+    with pytest.raises(tk.TuckerError) as e:
+        tk.tucker_init(c, v, [4, 5], [1, 1])
+    assert e.value.status == 2
+
+
+# ------------------------------------------------------------------------------------------
+# TTMc
+# ------------------------------------------------------------------------------------------
+
+TTMC_CASES = [
+    # dims, ranks, nnz   (several chunks, rows split across chunks, ragged tails, empty rows)
+    ([40, 300, 200], [16, 16, 16], 20000),     # order-3 MFMA path, long rows (split)
+    ([500, 80, 60], [10, 10, 10], 12000),      # R = 10 (padded tile), empty rows in mode 0
+    ([64, 48, 32], [8, 8, 8], 3000),
+    ([30, 20, 25, 12], [3, 4, 2, 3], 5000),    # order 4, generic path
+    ([12, 10, 9, 8, 7], [2, 3, 2, 2, 2], 2500),  # order 5
+    ([300, 250], [5, 7], 4000),                # order 2 (SpMM)
+    ([50, 40, 30], [20, 3, 17], 4000),         # R > 16: generic path for order 3
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("case", range(len(TTMC_CASES)))
+def test_ttmc_parity(tk, dtype, case):
+    dims, ranks, nnz = TTMC_CASES[case]
+    w = synth.small_uniform(100 + case, dims, ranks, nnz)
+    ctx = make(tk, w, dtype)
+    Ud = dev_list(w.U_init)
+    for mode in range(len(dims)):
+        Y = tk.ttmc_mode(ctx, mode, Ud).double().cpu().numpy()
+        Yo = oracle.ttmc(w.coords, w.vals, dims, ranks, mode, w.U_init)
+        err = rel_fro(Y, Yo)
+        assert err <= TOL_Y[dtype], (mode, err)
+        # same rounded inputs: only the accumulation differs
+        Yc = oracle.ttmc(w.coords, cast_vals(w.vals, dtype), dims, ranks, mode, cast_inputs(w.U_init, dtype))
+        assert rel_fro(Y, Yc) <= (1e-13 if dtype == "f64" else 2e-6), (mode, rel_fro(Y, Yc))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ttmc_degenerate(tk, dtype):
+    # a single nonzero; all nonzeros in one row; rank-1 factors
+    dims, ranks = [7, 6, 5], [1, 1, 1]
+    coords = np.array([[3], [2], [4]], dtype=np.int32)
+    w = synth.small_uniform(7, dims, ranks, 1)
+    ctx = tk.tucker_init(*to_dev(coords, np.array([2.5])), dims, ranks, dtype=dtype)
+    for mode in range(3):
+        Y = tk.ttmc_mode(ctx, mode, dev_list(w.U_init)).double().cpu().numpy()
+        Yo = oracle.ttmc(coords, np.array([2.5]), dims, ranks, mode, w.U_init)
+        assert rel_fro(Y, Yo) < TOL_Y[dtype]
+    rng = np.random.default_rng(3)
+    dims, ranks = [4, 100, 100], [4, 16, 16]
+    keys = rng.choice(100 * 100, size=5000, replace=False)
+    coords = np.stack([np.full(5000, 2), keys // 100, keys % 100]).astype(np.int32)
+    vals = rng.standard_normal(5000)
+    U = [synth.gaussian_qr(rng, d, r) for d, r in zip(dims, ranks)]
+    ctx = tk.tucker_init(*to_dev(coords, vals), dims, ranks, dtype=dtype)
+    Y = tk.ttmc_mode(ctx, 0, dev_list(U)).double().cpu().numpy()
+    Yo = oracle.ttmc(coords, vals, dims, ranks, 0, U)
+    assert rel_fro(Y, Yo) < TOL_Y[dtype]
+    assert np.all(Y[[0, 1, 3]] == 0)
+
+
+def test_ttmc_empty_tensor(tk):
+    dims, ranks = [5, 6, 7], [2, 2, 2]
+    c = torch.zeros((3, 0), dtype=torch.int32, device="cuda")
+    v = torch.zeros(0, dtype=torch.float64, device="cuda")
+    ctx = tk.tucker_init(c, v, dims, ranks, dtype="f32")
+    U = dev_list([np.ones((d, r)) for d, r in zip(dims, ranks)])
+    for mode in range(3):
+        Y = torch.full((dims[mode], 4), 7.0, dtype=torch.float32, device="cuda")
+        tk.ttmc_mode(ctx, mode, U, Y)
+        assert torch.count_nonzero(Y).item() == 0
+
+
+# ------------------------------------------------------------------------------------------
+# QRP, core, sweeps, reconstruct
+# ------------------------------------------------------------------------------------------
+
+def qrp_case(tk, dtype, dims, ranks, mode, nnz, seed, fat_rule=True):
+    w = synth.small_uniform(seed, dims, ranks, nnz)
+    ctx = make(tk, w, dtype, fat_rule)
+    Yo = oracle.ttmc(w.coords, w.vals, dims, ranks, mode, w.U_init)
+    yt = torch.float64 if dtype == "f64" else torch.float32
+    Yd = torch.from_numpy(Yo).to(yt).cuda().contiguous()
+    U, piv = tk.qrp_update(ctx, mode, Yd)
+    Ue, pe = oracle.factor(Yd.double().cpu().numpy(), ranks[mode], fat_rule=fat_rule)
+    return U.cpu().numpy(), piv.cpu().numpy(), Ue, pe
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", [
+    ([3000, 40, 30], [12, 8, 8], 0, 20000),   # tall, Gram route (K = 64)
+    ([2000, 60, 50], [16, 16, 16], 0, 30000), # tall, Gram route (K = 256)
+    ([200, 40, 30], [8, 8, 8], 0, 5000),      # small: Householder route
+    ([20, 30, 25, 40], [5, 4, 4, 4], 0, 6000),  # fat (K = 64 > 20): Householder on Y Y^T
+])
+def test_qrp_parity(tk, dtype, case):
+    dims, ranks, mode, nnz = case
+    U, piv, Ue, pe = qrp_case(tk, dtype, dims, ranks, mode, nnz, seed=200)
+    assert piv.tolist() == pe.tolist()
+    np.testing.assert_allclose(U, Ue, atol=1e-10)
+    np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+
+
+def test_qrp_rank_deficient_fallback(tk):
+    """Y of rank 3 with R = 5: the Gram route detects the deficiency and the Householder kernel
+    runs on the device.  Columns past the rank are set by round-off (parity unpinned); the first
+    3 pivots, the rank-3 subspace and orthonormality are checked."""
+    rng = np.random.default_rng(4)
+    dims, ranks = [3000, 10, 10], [5, 8, 8]
+    w = synth.small_uniform(9, dims, ranks, 100)
+    ctx = make(tk, w, "f64")
+    Y = rng.standard_normal((3000, 3)) @ rng.standard_normal((3, 64))
+    U, piv = tk.qrp_update(ctx, 0, torch.from_numpy(Y).cuda())
+    U = U.cpu().numpy()
+    Ue, pe = oracle.factor(Y, 5)
+    assert piv.cpu().numpy()[:3].tolist() == pe[:3].tolist()
+    np.testing.assert_allclose(U.T @ U, np.eye(5), atol=1e-12)
+    np.testing.assert_allclose(U[:, :3] @ (U[:, :3].T @ Y), Y, atol=1e-9 * np.abs(Y).max())
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_core_fit_parity(tk, dtype):
+    dims, ranks = [300, 200, 150], [8, 6, 5]
+    w = synth.small_uniform(300, dims, ranks, 8000)
+    ctx = make(tk, w, dtype)
+    Yo = oracle.ttmc(w.coords, w.vals, dims, ranks, 2, w.U_init)
+    yt = torch.float64 if dtype == "f64" else torch.float32
+    Yd = torch.from_numpy(Yo).to(yt).cuda()
+    G, fit = tk.core_fit(ctx, Yd, torch.from_numpy(w.U_init[2]).cuda())
+    Ge = oracle.core(Yd.double().cpu().numpy(), w.U_init[2], ranks)
+    assert rel_fro(G.cpu().numpy(), Ge) < 1e-13
+    fe = oracle.fit(float(w.vals @ w.vals), Ge)
+    assert abs(fit.item() - fe) < 1e-12
+
+
+def test_hooi_sweeps_f64_200cube(tk):
+    """The FP64 workload (200^3, 20,000 nnz, ranks 8, 5 sweeps): fits, factors and core match."""
+    w = synth.hooi_small_f64(1)
+    Uo, Go, fo, po = oracle.hooi(w.coords, w.vals, w.dims, w.ranks, w.U_init, w.sweeps)
+    ctx = make(tk, w, "f64")
+    U = dev_list(w.U_init)
+    fits = []
+    for _ in range(w.sweeps):
+        G, f = tk.hooi_sweep(ctx, U, sync_fit=True)
+        fits.append(f)
+    np.testing.assert_allclose(fits, fo, rtol=1e-12, atol=0)
+    for k in range(3):
+        np.testing.assert_allclose(U[k].cpu().numpy(), Uo[k], atol=1e-10)
+    assert rel_fro(G.cpu().numpy(), Go) < 1e-10
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 1e-2)])
+def test_hooi_sweeps_lowrank_small(tk, dtype, tol):
+    """Order-3 low-rank + noise (the large FP32 workload's recipe at a small size): sweep fits match
+    the FP64 oracle within the stated relative tolerance; factors span the same subspaces."""
+    w = synth.lowrank_f32(seed=12, dims=(3000, 2500, 2000), nnz=200000, R=16, noise=1e-3, sweeps=3)
+    Uo, Go, fo, _ = oracle.hooi(w.coords, w.vals, w.dims, w.ranks, w.U_init, w.sweeps)
+    ctx = make(tk, w, dtype)
+    U = dev_list(w.U_init)
+    fits = [tk.hooi_sweep(ctx, U, sync_fit=True)[1] for _ in range(w.sweeps)]
+    rel = np.abs(np.array(fits) - fo) / np.abs(fo)
+    assert np.all(rel <= tol), (fits, fo)
+    for k in range(3):
+        P = U[k].cpu().numpy()
+        assert np.linalg.norm(P @ P.T - Uo[k] @ Uo[k].T) < (1e-4 if dtype == "f32" else 0.5)
+
+
+def test_hooi_order4_f32(tk):
+    w = synth.order4(seed=13, dims=(400, 300, 60, 20), nnz=30000, R=4, sweeps=2)
+    Uo, Go, fo, _ = oracle.hooi(w.coords, w.vals, w.dims, w.ranks, w.U_init, w.sweeps)
+    ctx = make(tk, w, "f32")
+    U = dev_list(w.U_init)
+    fits = [tk.hooi_sweep(ctx, U, sync_fit=True)[1] for _ in range(w.sweeps)]
+    np.testing.assert_allclose(fits, fo, rtol=1e-5)
+
+
+def test_reconstruct_parity(tk):
+    rng = np.random.default_rng(500)
+    dims, ranks = [60, 50, 40, 30], [3, 4, 2, 5]
+    w = synth.small_uniform(500, dims, ranks, 100)
+    ctx = make(tk, w, "f64")
+    G = rng.standard_normal(ranks)
+    U = [rng.standard_normal((d, r)) for d, r in zip(dims, ranks)]
+    coords = np.stack([rng.integers(0, d, 5000) for d in dims]).astype(np.int32)
+    out = tk.reconstruct(ctx, torch.from_numpy(G).cuda(), dev_list(U), torch.from_numpy(coords).cuda())
+    np.testing.assert_allclose(out.cpu().numpy(), oracle.reconstruct(G, U, coords), rtol=1e-13, atol=1e-13)
