@@ -26,7 +26,8 @@ __global__ void k_convert_factor(const double* __restrict__ U, int64_t I, int R,
     else out[e] = f32_to_bf16((float)u);
 }
 
-// part[split][r][c] = sum_{i in slab} U[i][r] * Y[i][c]; thread per column c, 16 r's per z-block.
+// part[split][r][c] = sum_{i in slab} U[i][r] * Y[i][c]; thread per column c, 16 r's per z-block,
+// 4 rows of the slab in flight per iteration.
 template <typename YT>
 __global__ __launch_bounds__(256) void k_core_partial(const YT* __restrict__ Y, const double* __restrict__ U,
                                                       int64_t I, int K, int R, int64_t slab,
@@ -39,36 +40,50 @@ __global__ __launch_bounds__(256) void k_core_partial(const YT* __restrict__ Y, 
     double acc[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-    if (c < K) {
-        for (int64_t i = i0; i < i1; ++i) {
-            const double y = (double)Y[i * K + c];
+    if (c >= K) return;
+    int64_t i = i0;
+    for (; i + 4 <= i1; i += 4) {
+        double y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = (double)Y[(i + u) * K + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                if (rb + r < R) acc[r] += U[i * R + rb + r] * y;
-        }
+                if (rb + r < R) acc[r] += U[(i + u) * R + rb + r] * y[u];
+    }
+    for (; i < i1; ++i) {
+        const double y = (double)Y[i * K + c];
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            if (rb + r < R) part[((int64_t)split * R + rb + r) * K + c] = acc[r];
+            if (rb + r < R) acc[r] += U[i * R + rb + r] * y;
     }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (rb + r < R) part[((int64_t)split * R + rb + r) * K + c] = acc[r];
 }
 
-// G[c * R + r] = sum_split part[split][r][c] in split order; then ||G||^2 and the fit.
-__global__ __launch_bounds__(1024) void k_core_finish(const double* __restrict__ part, int nsplit, int K, int R,
-                                                      double normx2, double* __restrict__ G,
-                                                      double* __restrict__ fit) {
+// G[c * R + r] = sum_split part[split][r][c], summed in split order.
+__global__ void k_core_reduce(const double* __restrict__ part, int nsplit, int K, int R,
+                              double* __restrict__ G) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)K * R) return;
+    const int c = (int)(e / R), r = (int)(e % R);
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[((int64_t)k * R + r) * K + c];
+    G[e] = s;
+}
+
+// ||G||^2 (fixed-order tree) and fit = 1 - sqrt(max(||X||^2 - ||G||^2, 0)) / ||X||.
+__global__ __launch_bounds__(1024) void k_core_fit(const double* __restrict__ G, int64_t size, double normx2,
+                                                   double* __restrict__ fit) {
     __shared__ double red[16];
     double g2 = 0.0;
-    for (int64_t e = threadIdx.x; e < (int64_t)K * R; e += blockDim.x) {
-        const int c = (int)(e / R), r = (int)(e % R);
-        double s = 0.0;
-        for (int k = 0; k < nsplit; ++k) s += part[((int64_t)k * R + r) * K + c];
-        G[e] = s;
-        g2 += s * s;
-    }
+    for (int64_t e = threadIdx.x; e < size; e += blockDim.x) g2 += G[e] * G[e];
     for (int o = 32; o > 0; o >>= 1) g2 += __shfl_xor(g2, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g2;
     __syncthreads();
-    if (threadIdx.x == 0 && fit) {
+    if (threadIdx.x == 0) {
         double s = 0.0;
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
         double r2 = normx2 - s;
@@ -141,7 +156,7 @@ static void core_plan(const tk_ctx* ctx, int& nsplit, int64_t& slab) {
     const int64_t I = ctx->dims[n];
     const int64_t K = ctx->mode[n].K;
     const int64_t cblocks = (K + 255) / 256;
-    nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(cblocks, 1), (I + 63) / 64));
+    nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(1024 / std::max<int64_t>(cblocks, 1), (I + 31) / 32));
     slab = (I + nsplit - 1) / nsplit;
     nsplit = (int)((I + slab - 1) / slab);
 }
@@ -169,8 +184,12 @@ int core_run(tk_ctx* ctx, const void* Y, const double* U, double* G, double* fit
     else
         k_core_partial<float><<<grid, 256, 0, s>>>((const float*)Y, U, I, K, R, slab, part);
     TK_LAUNCH_CHECK("k_core_partial");
-    k_core_finish<<<1, 1024, 0, s>>>(part, nsplit, K, R, ctx->normx2, G, fit);
-    TK_LAUNCH_CHECK("k_core_finish");
+    k_core_reduce<<<cdiv((int64_t)K * R, 256), 256, 0, s>>>(part, nsplit, K, R, G);
+    TK_LAUNCH_CHECK("k_core_reduce");
+    if (fit) {
+        k_core_fit<<<1, 1024, 0, s>>>(G, (int64_t)K * R, ctx->normx2, fit);
+        TK_LAUNCH_CHECK("k_core_fit");
+    }
     return TK_OK;
 }
 

@@ -37,7 +37,8 @@ __device__ inline double yld(const YT* Y, int64_t i) { return (double)Y[i]; }
 // ---- Route 0 -------------------------------------------------------------------------------
 
 // Partial C for one 64x64 block pair (bi <= bj) over one slab of rows.  Wave w computes the 16
-// rows bi*64+16w.. of the block, 4 MFMA tiles across bj's 64 columns.
+// rows bi*64+16w.. of the block, 4 MFMA tiles across bj's 64 columns.  In v_mfma_f64_16x16x4f64
+// lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds D[l/16 + 4v][l%16] in result v.
 template <typename YT>
 __global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, int64_t m, int n,
                                                       int nb, int64_t slab, double* __restrict__ part) {
@@ -51,26 +52,36 @@ __global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, 
     const int64_t r0 = (int64_t)split * slab;
     const int64_t r1 = min(m, r0 + slab);
     const int ca = bi * 64 + 16 * w + c16;
+    const bool cav = ca < n;
+    bool cbv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cbv[t] = (bj * 64 + 16 * t + c16) < n;
     d4_t acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = d4_t{0, 0, 0, 0};
-    for (int64_t r = r0; r < r1; r += 4) {
-        const int64_t row = r + kq;
-        const bool rv = row < r1;
-        const double a = (rv && ca < n) ? yld(Y, row * n + ca) : 0.0;
+    for (int64_t r = r0; r < r1; r += 16) {
+        double av[4], bv[4][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int cb = bj * 64 + 16 * t + c16;
-            const double bvl = (rv && cb < n) ? yld(Y, row * n + cb) : 0.0;
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bvl, acc[t], 0, 0, 0);
+        for (int u = 0; u < 4; ++u) {
+            const int64_t row = r + 4 * u + kq;
+            const bool rv = row < r1;
+            av[u] = (rv && cav) ? yld(Y, row * n + ca) : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                bv[u][t] = (rv && cbv[t]) ? yld(Y, row * n + bj * 64 + 16 * t + c16) : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][t], acc[t], 0, 0, 0);
     }
     double* P = part + (int64_t)split * n * n;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int i = bi * 64 + 16 * w + 4 * kq + v;
+            const int i = bi * 64 + 16 * w + kq + 4 * v;
             const int j = bj * 64 + 16 * t + c16;
             if (i < n && j < n) P[(int64_t)i * n + j] = acc[t][v];
         }
@@ -86,21 +97,25 @@ __global__ void k_gram_reduce(const double* __restrict__ part, int nsplit, int n
     C[e] = s;
 }
 
-// Pivoted Cholesky of C (n <= 1024), R steps, one workgroup.
+// Pivoted Cholesky of C (n <= 1024), R steps, one workgroup of 1024 threads; thread t owns
+// position t of the (physically swapped) column order.  L (n x R) lives in LDS when it fits
+// (lds_L != 0), else in the global workspace.  C is symmetric, so column cs is read as row cs.
 __global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, int n, int R,
-                                                  double* __restrict__ L, double* __restrict__ R11,
+                                                  double* __restrict__ Lg, int lds_L,
+                                                  double* __restrict__ R11,
                                                   int32_t* __restrict__ pivw, int32_t* __restrict__ flag) {
+    extern __shared__ double Ls[];
     __shared__ double d[1024];
     __shared__ int perm[1024];
-    __shared__ double lrow[64];
-    __shared__ double rv[32];
-    __shared__ int rp[32];
+    __shared__ double lrow[32];
+    __shared__ double rv[16];
+    __shared__ int rp[16];
     __shared__ double dmax0;
+    double* L = lds_L ? Ls : Lg;
     const int tid = threadIdx.x;
     if (tid < n) { d[tid] = C[(int64_t)tid * n + tid]; perm[tid] = tid; }
     if (tid == 0) *flag = 0;
     __syncthreads();
-    // largest initial diagonal (scale for the rank test)
     {
         double v = (tid < n) ? d[tid] : -1.0;
         for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -108,14 +123,13 @@ __global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, 
         __syncthreads();
         if (tid == 0) {
             double mx = rv[0];
-            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) mx = fmax(mx, rv[k]);
+            for (int k = 1; k < 16; ++k) mx = fmax(mx, rv[k]);
             dmax0 = mx;
         }
         __syncthreads();
     }
     bool bad = false;
     for (int j = 0; j < R; ++j) {
-        // first maximum of d over positions j..n-1 of the current order
         double v = -1.0;
         int p = n;
         if (tid >= j && tid < n) { v = d[perm[tid]]; p = tid; }
@@ -129,7 +143,7 @@ __global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, 
         if (tid == 0) {
             double bv = rv[0];
             int bp = rp[0];
-            for (int k = 1; k < (int)(blockDim.x >> 6); ++k)
+            for (int k = 1; k < 16; ++k)
                 if (rv[k] > bv || (rv[k] == bv && rp[k] < bp)) { bv = rv[k]; bp = rp[k]; }
             int t = perm[j]; perm[j] = perm[bp]; perm[bp] = t;
         }
@@ -139,13 +153,13 @@ __global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, 
         if (!(djj > 1e-12 * dmax0)) bad = true;
         const double ljj = bad ? 1.0 : sqrt(djj);
         if (tid < j) lrow[tid] = L[(int64_t)cs * R + tid];
-        if (tid == 0) L[(int64_t)cs * R + j] = ljj;
         __syncthreads();
+        if (tid == 0) L[(int64_t)cs * R + j] = ljj;
         if (tid > j && tid < n) {
             const int c = perm[tid];
-            double sacc = C[(int64_t)c * n + cs];
-            for (int i = 0; i < j; ++i) sacc -= L[(int64_t)c * R + i] * lrow[i];
-            const double l = sacc / ljj;
+            double acc = C[(int64_t)cs * n + c];
+            for (int i = 0; i < j; ++i) acc -= L[(int64_t)c * R + i] * lrow[i];
+            const double l = acc / ljj;
             L[(int64_t)c * R + j] = l;
             d[c] -= l * l;
         }
@@ -210,8 +224,9 @@ __global__ __launch_bounds__(256) void k_q1_gram(const YT* __restrict__ Y, int64
     }
 }
 
-// Sum the Gram partials, Cholesky them, fold in R11^{-1}, fix the Householder signs.
-// M = R11^{-1} R2^{-1} S  (so that U = Y[:, piv] M).  Single thread does the R x R algebra.
+// Sum the Gram partials, Cholesky them, fold in R11^{-1}, fix the Householder signs:
+// M = R11^{-1} R2^{-1} S, so that U = Y[:, piv] M.  One workgroup; the R x R algebra is spread
+// over threads (one column or row of the triangular solves per thread).
 template <typename YT>
 __global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, int n, int R,
                                                     const int32_t* __restrict__ pivw,
@@ -220,73 +235,89 @@ __global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, in
                                                     int32_t* __restrict__ flag, double* __restrict__ Mout,
                                                     int32_t* __restrict__ piv_out) {
     if (*flag) return;
-    __shared__ double G2[32 * 32];
-    __shared__ double A[32 * 32];
-    __shared__ double B[32 * 32];
+    __shared__ double G2[32 * 32];   // Gram of Q1, then M' = R11^{-1} R2^{-1}
+    __shared__ double A[32 * 32];    // R2 (upper)
+    __shared__ double Bi[32 * 32];   // R11^{-1} (upper)
+    __shared__ double T[32 * 32];    // top R x R block of Y[:, piv] M', then its LU
+    __shared__ double Bt[32 * 32];   // Y[0:R, piv]
+    __shared__ double R1[32 * 32];
+    __shared__ double sgn[32];
+    __shared__ int bad;
     const int tid = threadIdx.x;
     for (int e = tid; e < R * R; e += 256) {
-        double sacc = 0.0;
-        for (int k = 0; k < nblk; ++k) sacc += part2[(int64_t)k * R * R + e];
-        G2[e] = sacc;
+        double acc = 0.0;
+        for (int k = 0; k < nblk; ++k) acc += part2[(int64_t)k * R * R + e];
+        G2[e] = acc;
+        A[e] = 0.0;
+        R1[e] = R11[e];
+        Bt[e] = yld(Y, (int64_t)(e / R) * n + pivw[e % R]);
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    // Cholesky G2 = R2^T R2, row j of R2 per step
+    for (int j = 0; j < R; ++j) {
+        if (tid == 0) {
+            double d = G2[j * R + j];
+            for (int k = 0; k < j; ++k) d -= A[k * R + j] * A[k * R + j];
+            if (!(d > 0.0)) bad = 1;
+            A[j * R + j] = (d > 0.0) ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const int c = j + 1 + tid;
+        if (c < R) {
+            double acc = G2[j * R + c];
+            for (int k = 0; k < j; ++k) acc -= A[k * R + j] * A[k * R + c];
+            A[j * R + c] = acc / A[j * R + j];
+        }
+        __syncthreads();
+    }
+    // Bi = R11^{-1}: column c by back substitution (thread c)
+    if (tid < R) {
+        const int c = tid;
+        for (int i = R - 1; i >= 0; --i) {
+            double acc = (i == c) ? 1.0 : 0.0;
+            for (int k = i + 1; k < R; ++k) acc -= R1[i * R + k] * Bi[k * R + c];
+            Bi[i * R + c] = acc / R1[i * R + i];
+        }
     }
     __syncthreads();
-    if (tid != 0) return;
-    // Cholesky G2 = R2^T R2 (upper R2 stored in A)
-    for (int i = 0; i < R * R; ++i) A[i] = 0.0;
-    for (int j = 0; j < R; ++j) {
-        double djj = G2[j * R + j];
-        for (int k = 0; k < j; ++k) djj -= A[k * R + j] * A[k * R + j];
-        if (!(djj > 0.0)) { *flag = 1; return; }
-        const double rjj = sqrt(djj);
-        A[j * R + j] = rjj;
-        for (int c = j + 1; c < R; ++c) {
-            double sacc = G2[j * R + c];
-            for (int k = 0; k < j; ++k) sacc -= A[k * R + j] * A[k * R + c];
-            A[j * R + c] = sacc / rjj;
-        }
-    }
-    // B = R11^{-1} (upper), then G2 <- B * R2^{-1} = M'
-    for (int i = 0; i < R * R; ++i) B[i] = 0.0;
-    for (int c = 0; c < R; ++c) {          // solve R11 x = e_c (upper)
-        for (int i = R - 1; i >= 0; --i) {
-            double sacc = (i == c) ? 1.0 : 0.0;
-            for (int k = i + 1; k < R; ++k) sacc -= R11[i * R + k] * B[k * R + c];
-            B[i * R + c] = sacc / R11[i * R + i];
-        }
-    }
-    // M' = B R2^{-1}: solve M' R2 = B row by row (forward over columns)
-    for (int i = 0; i < R; ++i)
+    // M' = Bi R2^{-1}: row i by forward substitution over columns (thread i)
+    if (tid < R) {
+        const int i = tid;
         for (int c = 0; c < R; ++c) {
-            double sacc = B[i * R + c];
-            for (int k = 0; k < c; ++k) sacc -= G2[i * R + k] * A[k * R + c];
-            G2[i * R + c] = sacc / A[c * R + c];
-        }
-    // T = top R x R block of Q1' = Y[0:R, piv] M'
-    for (int i = 0; i < R; ++i)
-        for (int c = 0; c < R; ++c) {
-            double sacc = 0.0;
-            for (int k = 0; k < R; ++k) sacc += yld(Y, (int64_t)i * n + pivw[k]) * G2[k * R + c];
-            B[i * R + c] = sacc;
-        }
-    // sign rule: LU of (T S - I) without pivoting, choosing s_j so that the pivot is <= -1
-    double* sgn = A;  // R2 is no longer needed
-    for (int j = 0; j < R; ++j) {
-        const double pv = B[j * R + j];
-        const double sj = (pv >= 0.0) ? -1.0 : 1.0;
-        sgn[j] = sj;
-        for (int i = 0; i < R; ++i) B[i * R + j] *= sj;
-        B[j * R + j] -= 1.0;
-        const double piv = B[j * R + j];
-        for (int i = j + 1; i < R; ++i) {
-            const double l = B[i * R + j] / piv;
-            for (int c = j + 1; c < R; ++c) B[i * R + c] -= l * B[j * R + c];
-            B[i * R + j] = l;
+            double acc = Bi[i * R + c];
+            for (int k = 0; k < c; ++k) acc -= G2[i * R + k] * A[k * R + c];
+            G2[i * R + c] = acc / A[c * R + c];
         }
     }
-    for (int k = 0; k < R; ++k)
-        for (int c = 0; c < R; ++c) Mout[k * R + c] = G2[k * R + c] * sgn[c];
-    if (piv_out)
-        for (int j = 0; j < R; ++j) piv_out[j] = pivw[j];
+    __syncthreads();
+    // T = Bt M'
+    for (int e = tid; e < R * R; e += 256) {
+        const int i = e / R, c = e % R;
+        double acc = 0.0;
+        for (int k = 0; k < R; ++k) acc += Bt[i * R + k] * G2[k * R + c];
+        T[e] = acc;
+    }
+    __syncthreads();
+    // sign rule: LU of (T S - I) without pivoting, s_j chosen so that the pivot is <= -1
+    for (int j = 0; j < R; ++j) {
+        if (tid == 0) sgn[j] = (T[j * R + j] >= 0.0) ? -1.0 : 1.0;
+        __syncthreads();
+        if (tid < R) {
+            T[tid * R + j] *= sgn[j];
+            if (tid == j) T[j * R + j] -= 1.0;
+        }
+        __syncthreads();
+        const double pv = T[j * R + j];
+        for (int e = tid; e < (R - j - 1) * (R - j - 1); e += 256) {
+            const int i = j + 1 + e / (R - j - 1), c = j + 1 + e % (R - j - 1);
+            T[i * R + c] -= (T[i * R + j] / pv) * T[j * R + c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < R * R; e += 256) Mout[e] = G2[e] * sgn[e % R];
+    if (piv_out && tid < R) piv_out[tid] = pivw[tid];
+    if (tid == 0 && bad) *flag = 1;
 }
 
 template <typename YT, typename LT>
@@ -504,8 +535,8 @@ QrpPlan plan(const tk_ctx* ctx, int mode) {
         p.nb = (p.n + 63) / 64;
         const int64_t nn = (int64_t)p.n * p.n;
         int64_t cap = std::max<int64_t>(1, (int64_t)(32u << 20) / 8 / nn);  // <= 32 MB of partials
-        p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(p.m + 511) / 512, 128, cap}));
-        p.slab = ((p.m + p.nsplit - 1) / p.nsplit + 3) / 4 * 4;
+        p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(p.m + 127) / 128, 256, cap}));
+        p.slab = ((p.m + p.nsplit - 1) / p.nsplit + 15) / 16 * 16;
         p.nsplit = (int)((p.m + p.slab - 1) / p.slab);
         p.rows2 = std::max<int64_t>(256, (p.m + 511) / 512);
         p.rows2 = (p.rows2 + 255) / 256 * 256;
@@ -545,7 +576,9 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
         TK_LAUNCH_CHECK("k_gram_partial");
         k_gram_reduce<<<cdiv((int64_t)p.n * p.n, 256), 256, 0, s>>>(W + p.o_part, p.nsplit, p.n, W + p.o_C);
         TK_LAUNCH_CHECK("k_gram_reduce");
-        k_pivchol<<<1, 1024, 0, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, W + p.o_R11, pivw, flag);
+        const size_t lsz = (size_t)p.n * p.R * sizeof(double);
+        const int lds_L = lsz <= 64 * 1024 ? 1 : 0;
+        k_pivchol<<<1, 1024, lds_L ? lsz : 0, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, lds_L, W + p.o_R11, pivw, flag);
         TK_LAUNCH_CHECK("k_pivchol");
         k_q1_gram<YT><<<(unsigned)p.nblk2, 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_R11, flag, p.rows2,
                                                          W + p.o_part2);

@@ -41,8 +41,6 @@ struct TtmcArgs {
     void* carry;
 };
 
-template <typename T> __device__ inline T ld_cvt(const void* p, int64_t i);
-template <> __device__ inline double ld_cvt<double>(const void* p, int64_t i) { return ((const double*)p)[i]; }
 template <typename ST> __device__ inline float ld_f32(const void* p, int64_t i);
 template <> __device__ inline float ld_f32<float>(const void* p, int64_t i) { return ((const float*)p)[i]; }
 template <> __device__ inline float ld_f32<bf16_t>(const void* p, int64_t i) { return bf16_to_f32(((const bf16_t*)p)[i]); }
@@ -51,6 +49,10 @@ template <typename AT, typename ST>
 __device__ inline AT load_as(const void* p, int64_t i) {
     if constexpr (sizeof(AT) == 8) return ((const double*)p)[i];
     else return ld_f32<ST>(p, i);
+}
+template <typename AT, typename ST>
+__device__ inline AT load_as(const ST* p, int64_t i) {
+    return load_as<AT, ST>((const void*)p, i);
 }
 
 // Zero the rows of Y strictly between the previous non-empty row and row s (and, for the last
@@ -69,31 +71,50 @@ __device__ inline void zero_gaps(const TtmcArgs& a, int s, int lane) {
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
+// 16x16x4 MFMA tiles: lane l supplies A[l%16][l/16] and B[l/16][l%16]; its 4 results hold
+// column l%16 of D, rows 4*(l/16)+v for the fp32 form and l/16+4*v for the fp64 form.
 template <typename AT> struct Acc;
 template <> struct Acc<float> {
     typedef f4_t type;
     static __device__ inline f4_t mfma(float a, float b, f4_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ inline int row(int kq, int v) { return 4 * kq + v; }
 };
 template <> struct Acc<double> {
     typedef d4_t type;
     static __device__ inline d4_t mfma(double a, double b, d4_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ inline int row(int kq, int v) { return kq + 4 * v; }
 };
 
+template <typename AT> struct Vec4;
+template <> struct Vec4<float> { typedef float4 type; };
+template <> struct Vec4<double> { typedef double4 type; };
+
+// Order-3 TTMc on MFMA.  A row segment is consumed in batches of 64 nonzeros: the 64 index pairs
+// and values are read coalesced (one per lane, the next batch prefetched), staged in the wave's
+// LDS slot, and lane group g = l/16 takes nonzeros 16g..16g+15 of the batch; step s of the 16
+// MFMAs contracts nonzeros {16g + s}.  All 32 factor gathers of a batch are issued before its
+// MFMAs.  The last, partial batch of a segment uses 4-nonzero steps (nonzero 4s + g).
 template <typename AT, typename ST>
 __global__ __launch_bounds__(256) void k_ttmc3_mfma(TtmcArgs a) {
+    __shared__ __align__(32) int32_t s_ia[4][64];
+    __shared__ __align__(32) int32_t s_ib[4][64];
+    __shared__ __align__(32) AT s_x[4][64];
     const int lane = threadIdx.x & 63;
-    const int ch = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int w = threadIdx.x >> 6;
+    const int ch = blockIdx.x * 4 + w;
     if (ch >= a.nchunks) return;
-    const int kq = lane >> 4;         // which of the 4 nonzeros of a step this lane carries
+    const int kq = lane >> 4;         // lane group: which nonzeros of a step this lane carries
     const int m = lane & 15;          // factor column carried by this lane
     const int q0 = a.chunk_ptr[ch], q1 = a.chunk_ptr[ch + 1];
     const int slot = a.chunk_slot[ch];
     const int32_t* __restrict__ ia = a.idx;
     const int32_t* __restrict__ ib = a.idx + a.nnz;
+    const ST* __restrict__ Fa = (const ST*)a.F[0] + m;
+    const ST* __restrict__ Fb = (const ST*)a.F[1] + m;
     const int Ra = a.R[0], Rb = a.R[1], K = a.K;
     int s = a.chunk_row[ch];
     int q = q0;
@@ -102,19 +123,67 @@ __global__ __launch_bounds__(256) void k_ttmc3_mfma(TtmcArgs a) {
         const int end = min(a.ptr[s + 1], q1);
         const bool owner = rs >= q0;
         typename Acc<AT>::type acc = {0, 0, 0, 0};
-        for (int p = q; p < end; p += 4) {
-            const int qq = p + kq;
-            const bool valid = qq < end;
-            const int qc = valid ? qq : end - 1;
-            const AT x = valid ? load_as<AT, ST>(a.val, qc) : AT(0);
-            const AT av = load_as<AT, ST>(a.F[0], (int64_t)ia[qc] * 16 + m) * x;
-            const AT bv = load_as<AT, ST>(a.F[1], (int64_t)ib[qc] * 16 + m);
-            acc = Acc<AT>::mfma(av, bv, acc);
+        int p = q;
+        const int nfull = (end - p) >> 6;
+        int pa = 0, pb = 0;
+        AT px = AT(0);
+        if (nfull > 0) {
+            pa = ia[p + lane];
+            pb = ib[p + lane];
+            px = load_as<AT, ST>(a.val, p + lane);
+        }
+        for (int b = 0; b < nfull; ++b) {
+            s_ia[w][lane] = pa;
+            s_ib[w][lane] = pb;
+            s_x[w][lane] = px;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (b + 1 < nfull) {
+                pa = ia[p + 64 + lane];
+                pb = ib[p + 64 + lane];
+                px = load_as<AT, ST>(a.val, p + 64 + lane);
+            }
+            int ja[16], jb[16];
+            AT xs[16];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int4 ta = *(const int4*)&s_ia[w][16 * kq + 4 * v];
+                const int4 tb = *(const int4*)&s_ib[w][16 * kq + 4 * v];
+                const typename Vec4<AT>::type tx = *(const typename Vec4<AT>::type*)&s_x[w][16 * kq + 4 * v];
+                ja[4 * v] = ta.x; ja[4 * v + 1] = ta.y; ja[4 * v + 2] = ta.z; ja[4 * v + 3] = ta.w;
+                jb[4 * v] = tb.x; jb[4 * v + 1] = tb.y; jb[4 * v + 2] = tb.z; jb[4 * v + 3] = tb.w;
+                xs[4 * v] = tx.x; xs[4 * v + 1] = tx.y; xs[4 * v + 2] = tx.z; xs[4 * v + 3] = tx.w;
+            }
+            AT av[16], bv[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                av[t] = load_as<AT, ST>(Fa, (int64_t)ja[t] * 16);
+                bv[t] = load_as<AT, ST>(Fb, (int64_t)jb[t] * 16);
+            }
+#pragma unroll
+            for (int t = 0; t < 16; ++t) acc = Acc<AT>::mfma(av[t] * xs[t], bv[t], acc);
+            p += 64;
+        }
+        // partial batch: 4-nonzero steps, in groups of 4 steps with their gathers issued first
+        for (; p < end; p += 16) {
+            AT av[4], bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int qq = p + 4 * t + kq;
+                const bool valid = qq < end;
+                const int qc = valid ? qq : end - 1;
+                const AT x = valid ? load_as<AT, ST>(a.val, qc) : AT(0);
+                av[t] = load_as<AT, ST>(Fa, (int64_t)ia[qc] * 16) * x;
+                bv[t] = load_as<AT, ST>(Fb, (int64_t)ib[qc] * 16);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = Acc<AT>::mfma(av[t], bv[t], acc);
         }
         AT* dst = owner ? (AT*)a.Y + (int64_t)a.rows[s] * K : (AT*)a.carry + (int64_t)slot * K;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int r = 4 * kq + v;
+            const int r = Acc<AT>::row(kq, v);
             if (r < Ra && m < Rb) dst[r * Rb + m] = acc[v];
         }
         if (owner) zero_gaps<AT>(a, s, lane);
