@@ -63,12 +63,13 @@ __global__ __launch_bounds__(256) void k_core_partial(const YT* __restrict__ Y, 
         if (rb + r < R) part[((int64_t)split * R + rb + r) * K + c] = acc[r];
 }
 
-// G[c * R + r] = sum_split part[split][r][c], summed in split order.
+// G[c * R + r] = sum_split part[split][r][c], summed in split order (thread e = r * K + c, so the
+// partial reads are coalesced).
 __global__ void k_core_reduce(const double* __restrict__ part, int nsplit, int K, int R,
                               double* __restrict__ G) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)K * R) return;
-    const int c = (int)(e / R), r = (int)(e % R);
+    const int r = (int)(e / K), c = (int)(e % K);
     double s = 0.0;
     for (int k = 0; k < nsplit; ++k) s += part[((int64_t)k * R + r) * K + c];
     G[e] = s;
@@ -156,7 +157,7 @@ static void core_plan(const tk_ctx* ctx, int& nsplit, int64_t& slab) {
     const int64_t I = ctx->dims[n];
     const int64_t K = ctx->mode[n].K;
     const int64_t cblocks = (K + 255) / 256;
-    nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(1024 / std::max<int64_t>(cblocks, 1), (I + 31) / 32));
+    nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(256 / std::max<int64_t>(cblocks, 1), (I + 63) / 64));
     slab = (I + nsplit - 1) / nsplit;
     nsplit = (int)((I + slab - 1) / slab);
 }

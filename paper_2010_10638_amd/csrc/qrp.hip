@@ -40,6 +40,19 @@ __device__ inline double yld(const YT* Y, int64_t i) { return (double)Y[i]; }
 // rows bi*64+16w.. of the block, 4 MFMA tiles across bj's 64 columns.  In v_mfma_f64_16x16x4f64
 // lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds D[l/16 + 4v][l%16] in result v.
 template <typename YT>
+__device__ inline void gram_load(const YT* __restrict__ Y, int64_t r, int64_t r1, int n, int kq, int ca,
+                                 bool cav, int cb0, const bool* cbv, double* av, double (*bv)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t row = r + 4 * u + kq;
+        const bool rv = row < r1;
+        av[u] = (rv && cav) ? yld(Y, row * n + ca) : 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[u][t] = (rv && cbv[t]) ? yld(Y, row * n + cb0 + 16 * t) : 0.0;
+    }
+}
+
+template <typename YT>
 __global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, int64_t m, int n,
                                                       int nb, int64_t slab, double* __restrict__ part) {
     // decode the upper-triangular block pair
@@ -53,28 +66,29 @@ __global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, 
     const int64_t r1 = min(m, r0 + slab);
     const int ca = bi * 64 + 16 * w + c16;
     const bool cav = ca < n;
+    const int cb0 = bj * 64 + c16;
     bool cbv[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) cbv[t] = (bj * 64 + 16 * t + c16) < n;
+    for (int t = 0; t < 4; ++t) cbv[t] = (cb0 + 16 * t) < n;
     d4_t acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = d4_t{0, 0, 0, 0};
+    double av[4], bv[4][4];
+    gram_load(Y, r0, r1, n, kq, ca, cav, cb0, cbv, av, bv);
     for (int64_t r = r0; r < r1; r += 16) {
-        double av[4], bv[4][4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t row = r + 4 * u + kq;
-            const bool rv = row < r1;
-            av[u] = (rv && cav) ? yld(Y, row * n + ca) : 0.0;
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                bv[u][t] = (rv && cbv[t]) ? yld(Y, row * n + bj * 64 + 16 * t + c16) : 0.0;
-        }
+        double an[4], bn[4][4];
+        gram_load(Y, r + 16, r1, n, kq, ca, cav, cb0, cbv, an, bn);   // rows past r1 load nothing
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][t], acc[t], 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            av[u] = an[u];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bv[u][t] = bn[u][t];
+        }
     }
     double* P = part + (int64_t)split * n * n;
 #pragma unroll
@@ -87,19 +101,23 @@ __global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, 
         }
 }
 
+// Sums the partials of entries in upper block pairs (bi <= bj) in split order and writes both
+// C[i][j] and its mirror C[j][i].
 __global__ void k_gram_reduce(const double* __restrict__ part, int nsplit, int n, double* __restrict__ C) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)n * n) return;
-    int i = (int)(e / n), j = (int)(e % n);
-    if ((i >> 6) > (j >> 6)) { int t = i; i = j; j = t; }
+    const int i = (int)(e / n), j = (int)(e % n);
+    if ((i >> 6) > (j >> 6)) return;
     double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n * n + (int64_t)i * n + j];
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n * n + e];
     C[e] = s;
+    if ((i >> 6) != (j >> 6)) C[(int64_t)j * n + i] = s;
 }
 
 // Pivoted Cholesky of C (n <= 1024), R steps, one workgroup of 1024 threads; thread t owns
-// position t of the (physically swapped) column order.  L (n x R) lives in LDS when it fits
-// (lds_L != 0), else in the global workspace.  C is symmetric, so column cs is read as row cs.
+// position t of the (physically swapped) column order.  L is stored transposed, entry (c, i) at
+// i * n + c, in LDS when it fits (lds_L != 0), else in the global workspace.  C is symmetric, so
+// column cs is read as row cs.
 __global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, int n, int R,
                                                   double* __restrict__ Lg, int lds_L,
                                                   double* __restrict__ R11,
@@ -152,15 +170,15 @@ __global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, 
         const double djj = d[cs];
         if (!(djj > 1e-12 * dmax0)) bad = true;
         const double ljj = bad ? 1.0 : sqrt(djj);
-        if (tid < j) lrow[tid] = L[(int64_t)cs * R + tid];
+        if (tid < j) lrow[tid] = L[(int64_t)tid * n + cs];
         __syncthreads();
-        if (tid == 0) L[(int64_t)cs * R + j] = ljj;
+        if (tid == 0) L[(int64_t)j * n + cs] = ljj;
         if (tid > j && tid < n) {
             const int c = perm[tid];
             double acc = C[(int64_t)cs * n + c];
-            for (int i = 0; i < j; ++i) acc -= L[(int64_t)c * R + i] * lrow[i];
+            for (int i = 0; i < j; ++i) acc -= L[(int64_t)i * n + c] * lrow[i];
             const double l = acc / ljj;
-            L[(int64_t)c * R + j] = l;
+            L[(int64_t)j * n + c] = l;
             d[c] -= l * l;
         }
         __syncthreads();
@@ -168,7 +186,7 @@ __global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, 
     if (tid < R) pivw[tid] = perm[tid];
     for (int e = tid; e < R * R; e += blockDim.x) {
         const int i = e / R, j = e % R;
-        R11[e] = (i <= j) ? L[(int64_t)perm[j] * R + i] : 0.0;
+        R11[e] = (i <= j) ? L[(int64_t)i * n + perm[j]] : 0.0;
     }
     if (bad && tid == 0) *flag = 1;
 }
@@ -226,7 +244,7 @@ __global__ __launch_bounds__(256) void k_q1_gram(const YT* __restrict__ Y, int64
 
 // Sum the Gram partials, Cholesky them, fold in R11^{-1}, fix the Householder signs:
 // M = R11^{-1} R2^{-1} S, so that U = Y[:, piv] M.  One workgroup; the R x R algebra is spread
-// over threads (one column or row of the triangular solves per thread).
+// over the threads of one wave (one column or row of the triangular solves per thread).
 template <typename YT>
 __global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, int n, int R,
                                                     const int32_t* __restrict__ pivw,
@@ -244,7 +262,8 @@ __global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, in
     __shared__ double sgn[32];
     __shared__ int bad;
     const int tid = threadIdx.x;
-    for (int e = tid; e < R * R; e += 256) {
+    const int nt = blockDim.x;
+    for (int e = tid; e < R * R; e += nt) {
         double acc = 0.0;
         for (int k = 0; k < nblk; ++k) acc += part2[(int64_t)k * R * R + e];
         G2[e] = acc;
@@ -292,7 +311,7 @@ __global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, in
     }
     __syncthreads();
     // T = Bt M'
-    for (int e = tid; e < R * R; e += 256) {
+    for (int e = tid; e < R * R; e += nt) {
         const int i = e / R, c = e % R;
         double acc = 0.0;
         for (int k = 0; k < R; ++k) acc += Bt[i * R + k] * G2[k * R + c];
@@ -309,13 +328,13 @@ __global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, in
         }
         __syncthreads();
         const double pv = T[j * R + j];
-        for (int e = tid; e < (R - j - 1) * (R - j - 1); e += 256) {
+        for (int e = tid; e < (R - j - 1) * (R - j - 1); e += nt) {
             const int i = j + 1 + e / (R - j - 1), c = j + 1 + e % (R - j - 1);
             T[i * R + c] -= (T[i * R + j] / pv) * T[j * R + c];
         }
         __syncthreads();
     }
-    for (int e = tid; e < R * R; e += 256) Mout[e] = G2[e] * sgn[e % R];
+    for (int e = tid; e < R * R; e += nt) Mout[e] = G2[e] * sgn[e % R];
     if (piv_out && tid < R) piv_out[tid] = pivw[tid];
     if (tid == 0 && bad) *flag = 1;
 }
@@ -352,16 +371,6 @@ __global__ __launch_bounds__(256) void k_form_u(const YT* __restrict__ Y, int64_
 
 // ---- Routes 1 and 2 ------------------------------------------------------------------------
 
-// A (m x n FP64, row-major) <- Y (gated: runs only when *gate == gate_val, gate may be NULL).
-template <typename YT>
-__global__ void k_copy_f64(const YT* __restrict__ Y, int64_t total, double* __restrict__ A,
-                           const int32_t* __restrict__ gate, int gate_val) {
-    if (gate && *gate != gate_val) return;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x)
-        A[e] = yld(Y, e);
-}
-
 // A = Y Y^T (I x I), FP64 accumulation.
 template <typename YT>
 __global__ void k_syrk_rows(const YT* __restrict__ Y, int I, int K, double* __restrict__ A) {
@@ -385,8 +394,8 @@ __device__ inline double block_sum(double v, double* red) {
 
 // Eager Householder QRP on A (m x n, FP64, in place), R steps, one workgroup of 1024 threads,
 // then Q[:, :R] = H_0 ... H_{R-1} [I; 0] into U (m x R) and the low-precision copy.
-template <typename LT>
-__global__ __launch_bounds__(1024) void k_house_qrp(double* __restrict__ A, int64_t m, int n, int R,
+template <typename YT, typename LT>
+__global__ __launch_bounds__(1024) void k_house_qrp(const YT* __restrict__ src, double* __restrict__ A, int64_t m, int n, int R,
                                                     double* __restrict__ V, double* __restrict__ w,
                                                     double* __restrict__ beta_s, int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ gate, int gate_val,
@@ -398,6 +407,8 @@ __global__ __launch_bounds__(1024) void k_house_qrp(double* __restrict__ A, int6
     __shared__ int rp[16];
     __shared__ int pbest;
     const int tid = threadIdx.x, nt = blockDim.x;
+    if (src)
+        for (int64_t e = tid; e < m * n; e += nt) A[e] = yld(src, e);
     for (int c = tid; c < n; c += nt) perm[c] = c;
     __syncthreads();
     for (int j = 0; j < R; ++j) {
@@ -535,7 +546,7 @@ QrpPlan plan(const tk_ctx* ctx, int mode) {
         p.nb = (p.n + 63) / 64;
         const int64_t nn = (int64_t)p.n * p.n;
         int64_t cap = std::max<int64_t>(1, (int64_t)(32u << 20) / 8 / nn);  // <= 32 MB of partials
-        p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(p.m + 127) / 128, 256, cap}));
+        p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(p.m + 255) / 256, 64, cap}));
         p.slab = ((p.m + p.nsplit - 1) / p.nsplit + 15) / 16 * 16;
         p.nsplit = (int)((p.m + p.slab - 1) / p.slab);
         p.rows2 = std::max<int64_t>(256, (p.m + 511) / 512);
@@ -583,15 +594,13 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
         k_q1_gram<YT><<<(unsigned)p.nblk2, 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_R11, flag, p.rows2,
                                                          W + p.o_part2);
         TK_LAUNCH_CHECK("k_q1_gram");
-        k_qrp_finish<YT><<<1, 256, 0, s>>>(Y, p.n, p.R, pivw, W + p.o_R11, W + p.o_part2, p.nblk2, flag,
+        k_qrp_finish<YT><<<1, 64, 0, s>>>(Y, p.n, p.R, pivw, W + p.o_R11, W + p.o_part2, p.nblk2, flag,
                                            W + p.o_M, piv);
         TK_LAUNCH_CHECK("k_qrp_finish");
         k_form_u<YT, LT><<<cdiv(p.m, 256), 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_M, flag, U, Ulp, ldlp);
         TK_LAUNCH_CHECK("k_form_u");
         // fallback, gated on the flag
-        k_copy_f64<YT><<<1024, 256, 0, s>>>(Y, I * K, W + p.o_A, flag, 1);
-        TK_LAUNCH_CHECK("k_copy_f64");
-        k_house_qrp<LT><<<1, 1024, 0, s>>>(W + p.o_A, I, (int)K, p.R, W + p.o_V, W + p.o_w, W + p.o_beta, perm, flag, 1, U,
+        k_house_qrp<YT, LT><<<1, 1024, 0, s>>>(Y, W + p.o_A, I, (int)K, p.R, W + p.o_V, W + p.o_w, W + p.o_beta, perm, flag, 1, U,
                                            Ulp, ldlp, piv);
         TK_LAUNCH_CHECK("k_house_qrp");
         return TK_OK;
@@ -599,11 +608,8 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
     if (p.route == 2) {
         k_syrk_rows<YT><<<cdiv(I * I, 256), 256, 0, s>>>(Y, (int)I, (int)K, W + p.o_A);
         TK_LAUNCH_CHECK("k_syrk_rows");
-    } else {
-        k_copy_f64<YT><<<1024, 256, 0, s>>>(Y, I * K, W + p.o_A, nullptr, 0);
-        TK_LAUNCH_CHECK("k_copy_f64");
     }
-    k_house_qrp<LT><<<1, 1024, 0, s>>>(W + p.o_A, p.m, p.n, p.R, W + p.o_V, W + p.o_w, W + p.o_beta, perm, nullptr, 0, U,
+    k_house_qrp<YT, LT><<<1, 1024, 0, s>>>(p.route == 2 ? nullptr : Y, W + p.o_A, p.m, p.n, p.R, W + p.o_V, W + p.o_w, W + p.o_beta, perm, nullptr, 0, U,
                                        Ulp, ldlp, piv);
     TK_LAUNCH_CHECK("k_house_qrp");
     return TK_OK;
