@@ -159,6 +159,8 @@ int tucker_init(tk_ctx** out, int order, const int64_t* dims, const int32_t* ran
         free_ctx(c);
         return st;
     }
+    // the QRP flag and the completion ticket of the Q1 Gram start at zero
+    if ((st = fill_zero(c->ws.qrp_int, c->ws.qrp_int_bytes, s))) { free_ctx(c); return st; }
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) { free_ctx(c); return hip_error(e, "tucker_init"); }
     c->last_stream = s;

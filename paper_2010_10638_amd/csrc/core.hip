@@ -1,6 +1,7 @@
 // Core tensor and fit (paper Alg. 2, the step after the mode loop; Sec. III-B unfolded form
 // G_(N) = U_N^T Y_(N)), sampled reconstruction of the Tucker model, factor conversions.
 #include "internal.h"
+#include "atb.h"
 
 namespace tk {
 
@@ -26,41 +27,31 @@ __global__ void k_convert_factor(const double* __restrict__ U, int64_t I, int R,
     else out[e] = f32_to_bf16((float)u);
 }
 
-// part[split][r][c] = sum_{i in slab} U[i][r] * Y[i][c]; thread per column c, 16 r's per z-block,
-// 4 rows of the slab in flight per iteration.
+// part[split][r][c] = sum_{i in slab} U[i][r] * Y[i][c] for r in a 64-block of U's columns and
+// c in a 64-block of Y's columns, on FP64 MFMA through LDS panels.
 template <typename YT>
 __global__ __launch_bounds__(256) void k_core_partial(const YT* __restrict__ Y, const double* __restrict__ U,
                                                       int64_t I, int K, int R, int64_t slab,
                                                       double* __restrict__ part) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    const int split = blockIdx.y;
-    const int rb = blockIdx.z * 16;
-    const int64_t i0 = (int64_t)split * slab;
-    const int64_t i1 = min(I, i0 + slab);
-    double acc[16];
+    __shared__ double As[2][32][65];
+    __shared__ double Bs[2][32][65];
+    const int b0 = blockIdx.x * 64, a0 = blockIdx.z * 64;
+    const int64_t r0 = (int64_t)blockIdx.y * slab;
+    const int64_t r1 = min(I, r0 + slab);
+    atb_d4_t acc[4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-    if (c >= K) return;
-    int64_t i = i0;
-    for (; i + 4 <= i1; i += 4) {
-        double y[4];
+    for (int t = 0; t < 4; ++t) acc[t] = atb_d4_t{0, 0, 0, 0};
+    atb_block<double, YT>(U, R, R, Y, K, K, r0, r1, a0, b0, As, Bs, acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kq = lane >> 4, c16 = lane & 15;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) y[u] = (double)Y[(i + u) * K + c];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (rb + r < R) acc[r] += U[(i + u) * R + rb + r] * y[u];
-    }
-    for (; i < i1; ++i) {
-        const double y = (double)Y[i * K + c];
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            if (rb + r < R) acc[r] += U[i * R + rb + r] * y;
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-        if (rb + r < R) part[((int64_t)split * R + rb + r) * K + c] = acc[r];
+        for (int v = 0; v < 4; ++v) {
+            const int r = a0 + 16 * w + kq + 4 * v;
+            const int c = b0 + 16 * t + c16;
+            if (r < R && c < K) part[((int64_t)blockIdx.y * R + r) * K + c] = acc[t][v];
+        }
 }
 
 // G[c * R + r] = sum_split part[split][r][c], summed in split order (thread e = r * K + c, so the
@@ -72,7 +63,7 @@ __global__ void k_core_reduce(const double* __restrict__ part, int nsplit, int K
     const int r = (int)(e / K), c = (int)(e % K);
     double s = 0.0;
     for (int k = 0; k < nsplit; ++k) s += part[((int64_t)k * R + r) * K + c];
-    G[e] = s;
+    G[(int64_t)c * R + r] = s;
 }
 
 // ||G||^2 (fixed-order tree) and fit = 1 - sqrt(max(||X||^2 - ||G||^2, 0)) / ||X||.
@@ -156,9 +147,9 @@ static void core_plan(const tk_ctx* ctx, int& nsplit, int64_t& slab) {
     const int n = ctx->N - 1;
     const int64_t I = ctx->dims[n];
     const int64_t K = ctx->mode[n].K;
-    const int64_t cblocks = (K + 255) / 256;
-    nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(256 / std::max<int64_t>(cblocks, 1), (I + 63) / 64));
-    slab = (I + nsplit - 1) / nsplit;
+    const int64_t cblocks = ((K + 63) / 64) * ((ctx->ranks[n] + 63) / 64);
+    nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(cblocks, 1), (I + 127) / 128));
+    slab = ((I + nsplit - 1) / nsplit + 31) / 32 * 32;
     nsplit = (int)((I + slab - 1) / slab);
 }
 
@@ -179,7 +170,7 @@ int core_run(tk_ctx* ctx, const void* Y, const double* U, double* G, double* fit
     int64_t slab;
     core_plan(ctx, nsplit, slab);
     double* part = ctx->ws.qrp;   // the QRP of the last mode has finished with its workspace
-    dim3 grid(cdiv(K, 256), (unsigned)nsplit, cdiv(R, 16));
+    dim3 grid(cdiv(K, 64), (unsigned)nsplit, cdiv(R, 64));
     if (ctx->dtype == TK_F64)
         k_core_partial<double><<<grid, 256, 0, s>>>((const double*)Y, U, I, K, R, slab, part);
     else

@@ -22,6 +22,7 @@
 // one workgroup: exact trailing-norm recompute, first-maximum pivot, v = x + sgn(x_0)||x|| e_1.
 // Route 2 (fat Y, K_n > I_n) - the same kernel on Y Y^T (I_n x I_n), as Sec. III-D prescribes.
 #include "internal.h"
+#include "atb.h"
 
 namespace tk {
 
@@ -39,58 +40,25 @@ __device__ inline double yld(const YT* Y, int64_t i) { return (double)Y[i]; }
 // Partial C for one 64x64 block pair (bi <= bj) over one slab of rows.  Wave w computes the 16
 // rows bi*64+16w.. of the block, 4 MFMA tiles across bj's 64 columns.  In v_mfma_f64_16x16x4f64
 // lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds D[l/16 + 4v][l%16] in result v.
-template <typename YT>
-__device__ inline void gram_load(const YT* __restrict__ Y, int64_t r, int64_t r1, int n, int kq, int ca,
-                                 bool cav, int cb0, const bool* cbv, double* av, double (*bv)[4]) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int64_t row = r + 4 * u + kq;
-        const bool rv = row < r1;
-        av[u] = (rv && cav) ? yld(Y, row * n + ca) : 0.0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) bv[u][t] = (rv && cbv[t]) ? yld(Y, row * n + cb0 + 16 * t) : 0.0;
-    }
-}
-
+// Gram partials: blockIdx.x enumerates the upper block pairs (bi <= bj) of 64-column blocks,
+// blockIdx.y the row slab.  part[split] holds the n x n partial (only upper-pair entries written).
 template <typename YT>
 __global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, int64_t m, int n,
                                                       int nb, int64_t slab, double* __restrict__ part) {
-    // decode the upper-triangular block pair
+    __shared__ double As[2][32][65];
+    __shared__ double Bs[2][32][65];
     int b = blockIdx.x, bi = 0;
     while (b >= nb - bi) { b -= nb - bi; ++bi; }
     const int bj = bi + b;
-    const int split = blockIdx.y;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int kq = lane >> 4, c16 = lane & 15;
-    const int64_t r0 = (int64_t)split * slab;
+    const int64_t r0 = (int64_t)blockIdx.y * slab;
     const int64_t r1 = min(m, r0 + slab);
-    const int ca = bi * 64 + 16 * w + c16;
-    const bool cav = ca < n;
-    const int cb0 = bj * 64 + c16;
-    bool cbv[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) cbv[t] = (cb0 + 16 * t) < n;
     d4_t acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = d4_t{0, 0, 0, 0};
-    double av[4], bv[4][4];
-    gram_load(Y, r0, r1, n, kq, ca, cav, cb0, cbv, av, bv);
-    for (int64_t r = r0; r < r1; r += 16) {
-        double an[4], bn[4][4];
-        gram_load(Y, r + 16, r1, n, kq, ca, cav, cb0, cbv, an, bn);   // rows past r1 load nothing
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][t], acc[t], 0, 0, 0);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            av[u] = an[u];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) bv[u][t] = bn[u][t];
-        }
-    }
-    double* P = part + (int64_t)split * n * n;
+    atb_block<YT, YT>(Y, n, n, Y, n, n, r0, r1, bi * 64, bj * 64, As, Bs, acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kq = lane >> 4, c16 = lane & 15;
+    double* P = part + (int64_t)blockIdx.y * n * n;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -120,7 +88,7 @@ __global__ void k_gram_reduce(const double* __restrict__ part, int nsplit, int n
 // column cs is read as row cs.
 __global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, int n, int R,
                                                   double* __restrict__ Lg, int lds_L,
-                                                  double* __restrict__ R11,
+                                                  double* __restrict__ R11, double* __restrict__ Rinv,
                                                   int32_t* __restrict__ pivw, int32_t* __restrict__ flag) {
     extern __shared__ double Ls[];
     __shared__ double d[1024];
@@ -184,62 +152,80 @@ __global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, 
         __syncthreads();
     }
     if (tid < R) pivw[tid] = perm[tid];
+    __shared__ double sR11[32 * 32];
     for (int e = tid; e < R * R; e += blockDim.x) {
         const int i = e / R, j = e % R;
-        R11[e] = (i <= j) ? L[(int64_t)i * n + perm[j]] : 0.0;
+        const double r = (i <= j) ? L[(int64_t)i * n + perm[j]] : 0.0;
+        R11[e] = r;
+        sR11[e] = r;
+    }
+    __syncthreads();
+    __shared__ double x[32][33];
+    if (tid < R) {  // column tid of R11^{-1} by back substitution
+        const int c = tid;
+        for (int i = R - 1; i >= 0; --i) {
+            double acc = (i == c) ? 1.0 : 0.0;
+            for (int k = i + 1; k <= c; ++k) acc -= sR11[i * R + k] * x[c][k];
+            x[c][i] = (i <= c) ? acc / sR11[i * R + i] : 0.0;
+            Rinv[i * R + c] = x[c][i];
+        }
     }
     if (bad && tid == 0) *flag = 1;
 }
 
-// Q1 = Y[:, piv] R11^{-1} row by row (forward substitution), and the partial Gram Q1^T Q1 of
-// this block's rows.
+// Q1 = Y[:, piv] R11^{-1} (one row per thread, as b times the precomputed upper-triangular
+// inverse, so the R outputs of a row are independent sums) and the partial Gram Q1^T Q1 of the
+// workgroup's 256 rows, one entry per thread.
 template <typename YT>
 __global__ __launch_bounds__(256) void k_q1_gram(const YT* __restrict__ Y, int64_t m, int n, int R,
                                                  const int32_t* __restrict__ pivw,
-                                                 const double* __restrict__ R11,
-                                                 const int32_t* __restrict__ flag, int64_t rows_per_block,
+                                                 const double* __restrict__ Rinv,
+                                                 const int32_t* __restrict__ flag,
                                                  double* __restrict__ part2) {
     if (*flag) return;
-    __shared__ double sR[32 * 32];
+    __shared__ double sRi[32 * 32];
     __shared__ int sp[32];
     __shared__ double q[256][33];
     const int tid = threadIdx.x;
-    for (int e = tid; e < R * R; e += 256) sR[e] = R11[e];
+    for (int e = tid; e < R * R; e += 256) sRi[e] = Rinv[e];
     if (tid < R) sp[tid] = pivw[tid];
     __syncthreads();
-    double g[4] = {0, 0, 0, 0};
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-    const int64_t r1 = min(m, r0 + rows_per_block);
-    for (int64_t base = r0; base < r1; base += 256) {
-        const int64_t row = base + tid;
-        if (row < r1) {
-            for (int j = 0; j < R; ++j) {
-                double sacc = yld(Y, row * n + sp[j]);
-                for (int i = 0; i < j; ++i) sacc -= q[tid][i] * sR[i * R + j];
-                q[tid][j] = sacc / sR[j * R + j];
-            }
-        } else {
-            for (int j = 0; j < R; ++j) q[tid][j] = 0.0;
-        }
-        __syncthreads();
-        const int nr = (int)min<int64_t>(256, r1 - base);
+    const int64_t row = (int64_t)blockIdx.x * 256 + tid;
+    double b[32];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int pr = tid + 256 * k;
-            if (pr < R * R) {
-                const int a = pr / R, b = pr % R;
-                double sacc = 0.0;
-                for (int rr = 0; rr < nr; ++rr) sacc += q[rr][a] * q[rr][b];
-                g[k] += sacc;
-            }
-        }
+    for (int j = 0; j < 32; ++j) b[j] = (j < R && row < m) ? yld(Y, row * n + sp[j]) : 0.0;
+    for (int c = 0; c < R; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            if (i <= c && i < R) acc += b[i] * sRi[i * R + c];
+        q[tid][c] = acc;
+    }
+    __syncthreads();
+    const int nr = (int)min<int64_t>(256, m - (int64_t)blockIdx.x * 256);
+    for (int pr = tid; pr < R * R; pr += 256) {
+        const int a = pr / R, bb = pr % R;
+        double acc = 0.0;
+        for (int rr = 0; rr < nr; ++rr) acc += q[rr][a] * q[rr][bb];
+        part2[(int64_t)blockIdx.x * R * R + pr] = acc;
+    }
+}
+
+// G2[e] = sum over workgroups of part2[k][e], one workgroup per entry, fixed-order tree.
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int nparts, int stride,
+                                                      const int32_t* __restrict__ flag, double* __restrict__ out) {
+    if (flag && *flag) return;
+    __shared__ double red[256];
+    const int e = blockIdx.x;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += 256) acc += part[(int64_t)k * stride + e];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int pr = tid + 256 * k;
-        if (pr < R * R) part2[(int64_t)blockIdx.x * R * R + pr] = g[k];
-    }
+    if (threadIdx.x == 0) out[e] = red[0];
 }
 
 // Sum the Gram partials, Cholesky them, fold in R11^{-1}, fix the Householder signs:
@@ -248,27 +234,24 @@ __global__ __launch_bounds__(256) void k_q1_gram(const YT* __restrict__ Y, int64
 template <typename YT>
 __global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, int n, int R,
                                                     const int32_t* __restrict__ pivw,
-                                                    const double* __restrict__ R11,
-                                                    const double* __restrict__ part2, int nblk,
+                                                    const double* __restrict__ Rinv,
+                                                    const double* __restrict__ G2in,
                                                     int32_t* __restrict__ flag, double* __restrict__ Mout,
                                                     int32_t* __restrict__ piv_out) {
     if (*flag) return;
     __shared__ double G2[32 * 32];   // Gram of Q1, then M' = R11^{-1} R2^{-1}
     __shared__ double A[32 * 32];    // R2 (upper)
-    __shared__ double Bi[32 * 32];   // R11^{-1} (upper)
+    __shared__ double Bi[32 * 32];   // R11^{-1} (upper), computed by k_pivchol
     __shared__ double T[32 * 32];    // top R x R block of Y[:, piv] M', then its LU
     __shared__ double Bt[32 * 32];   // Y[0:R, piv]
-    __shared__ double R1[32 * 32];
     __shared__ double sgn[32];
     __shared__ int bad;
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     for (int e = tid; e < R * R; e += nt) {
-        double acc = 0.0;
-        for (int k = 0; k < nblk; ++k) acc += part2[(int64_t)k * R * R + e];
-        G2[e] = acc;
+        G2[e] = G2in[e];
         A[e] = 0.0;
-        R1[e] = R11[e];
+        Bi[e] = Rinv[e];
         Bt[e] = yld(Y, (int64_t)(e / R) * n + pivw[e % R]);
     }
     if (tid == 0) bad = 0;
@@ -290,16 +273,6 @@ __global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, in
         }
         __syncthreads();
     }
-    // Bi = R11^{-1}: column c by back substitution (thread c)
-    if (tid < R) {
-        const int c = tid;
-        for (int i = R - 1; i >= 0; --i) {
-            double acc = (i == c) ? 1.0 : 0.0;
-            for (int k = i + 1; k < R; ++k) acc -= R1[i * R + k] * Bi[k * R + c];
-            Bi[i * R + c] = acc / R1[i * R + i];
-        }
-    }
-    __syncthreads();
     // M' = Bi R2^{-1}: row i by forward substitution over columns (thread i)
     if (tid < R) {
         const int i = tid;
@@ -339,6 +312,8 @@ __global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, in
     if (tid == 0 && bad) *flag = 1;
 }
 
+// U = Y[:, piv] M and its low-precision copy; 16 consecutive threads share a row, one output
+// column each (columns R..ldlp-1 of the copy are zeroed).
 template <typename YT, typename LT>
 __global__ __launch_bounds__(256) void k_form_u(const YT* __restrict__ Y, int64_t m, int n, int R,
                                                 const int32_t* __restrict__ pivw,
@@ -351,22 +326,17 @@ __global__ __launch_bounds__(256) void k_form_u(const YT* __restrict__ Y, int64_
     for (int e = threadIdx.x; e < R * R; e += 256) sM[e] = M[e];
     if (threadIdx.x < R) sp[threadIdx.x] = pivw[threadIdx.x];
     __syncthreads();
-    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t row = g / ldlp;
+    const int c = (int)(g % ldlp);
     if (row >= m) return;
-    double b[32];
-#pragma unroll
-    for (int j = 0; j < 32; ++j) b[j] = (j < R) ? yld(Y, row * n + sp[j]) : 0.0;
-    for (int c = 0; c < R; ++c) {
-        double u = 0.0;
-#pragma unroll
-        for (int j = 0; j < 32; ++j)
-            if (j < R) u += b[j] * sM[j * R + c];
-        U[row * R + c] = u;
-        if constexpr (sizeof(LT) == 8) Ulp[row * ldlp + c] = u;
-        else if constexpr (sizeof(LT) == 4) Ulp[row * ldlp + c] = (float)u;
-        else Ulp[row * ldlp + c] = f32_to_bf16((float)u);
-    }
-    for (int c = R; c < ldlp; ++c) Ulp[row * ldlp + c] = LT(0);
+    double u = 0.0;
+    if (c < R)
+        for (int j = 0; j < R; ++j) u += yld(Y, row * n + sp[j]) * sM[j * R + c];
+    if (c < R) U[row * R + c] = u;
+    if constexpr (sizeof(LT) == 8) Ulp[row * ldlp + c] = u;
+    else if constexpr (sizeof(LT) == 4) Ulp[row * ldlp + c] = (float)u;
+    else Ulp[row * ldlp + c] = f32_to_bf16((float)u);
 }
 
 // ---- Routes 1 and 2 ------------------------------------------------------------------------
@@ -521,7 +491,7 @@ struct QrpPlan {
     int nblk2;       // blocks of the Q1 Gram (route 0)
     int64_t rows2;
     // offsets into the FP64 workspace (in doubles)
-    int64_t o_part, o_C, o_L, o_R11, o_part2, o_M, o_A, o_V, o_w, o_beta;
+    int64_t o_part, o_C, o_L, o_R11, o_Rinv, o_part2, o_G2, o_M, o_A, o_V, o_w, o_beta;
     int64_t total;
 };
 
@@ -546,17 +516,20 @@ QrpPlan plan(const tk_ctx* ctx, int mode) {
         p.nb = (p.n + 63) / 64;
         const int64_t nn = (int64_t)p.n * p.n;
         int64_t cap = std::max<int64_t>(1, (int64_t)(32u << 20) / 8 / nn);  // <= 32 MB of partials
-        p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(p.m + 255) / 256, 64, cap}));
-        p.slab = ((p.m + p.nsplit - 1) / p.nsplit + 15) / 16 * 16;
+        const int64_t pairs = (int64_t)p.nb * (p.nb + 1) / 2;
+        const int64_t want = std::max<int64_t>(1, 768 / pairs);   // about 768 workgroups
+        p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(p.m + 127) / 128, want, cap}));
+        p.slab = ((p.m + p.nsplit - 1) / p.nsplit + 31) / 32 * 32;
         p.nsplit = (int)((p.m + p.slab - 1) / p.slab);
-        p.rows2 = std::max<int64_t>(256, (p.m + 511) / 512);
-        p.rows2 = (p.rows2 + 255) / 256 * 256;
-        p.nblk2 = (int)((p.m + p.rows2 - 1) / p.rows2);
+        p.rows2 = 256;
+        p.nblk2 = (int)((p.m + 255) / 256);
         p.o_part = off; off += (int64_t)p.nsplit * nn;
         p.o_C = off; off += nn;
         p.o_L = off; off += (int64_t)p.n * R;
         p.o_R11 = off; off += (int64_t)R * R;
+        p.o_Rinv = off; off += (int64_t)R * R;
         p.o_part2 = off; off += (int64_t)p.nblk2 * R * R;
+        p.o_G2 = off; off += (int64_t)R * R;
         p.o_M = off; off += (int64_t)R * R;
     }
     // Householder workspace (route 1/2, and the route-0 fallback on Y)
@@ -589,15 +562,16 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
         TK_LAUNCH_CHECK("k_gram_reduce");
         const size_t lsz = (size_t)p.n * p.R * sizeof(double);
         const int lds_L = lsz <= 64 * 1024 ? 1 : 0;
-        k_pivchol<<<1, 1024, lds_L ? lsz : 0, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, lds_L, W + p.o_R11, pivw, flag);
+        k_pivchol<<<1, 1024, lds_L ? lsz : 0, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, lds_L, W + p.o_R11, W + p.o_Rinv,
+                                                     pivw, flag);
         TK_LAUNCH_CHECK("k_pivchol");
-        k_q1_gram<YT><<<(unsigned)p.nblk2, 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_R11, flag, p.rows2,
-                                                         W + p.o_part2);
+        k_q1_gram<YT><<<(unsigned)p.nblk2, 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_Rinv, flag, W + p.o_part2);
         TK_LAUNCH_CHECK("k_q1_gram");
-        k_qrp_finish<YT><<<1, 64, 0, s>>>(Y, p.n, p.R, pivw, W + p.o_R11, W + p.o_part2, p.nblk2, flag,
-                                           W + p.o_M, piv);
+        k_sum_partials<<<(unsigned)(p.R * p.R), 256, 0, s>>>(W + p.o_part2, p.nblk2, p.R * p.R, flag, W + p.o_G2);
+        TK_LAUNCH_CHECK("k_sum_partials");
+        k_qrp_finish<YT><<<1, 256, 0, s>>>(Y, p.n, p.R, pivw, W + p.o_Rinv, W + p.o_G2, flag, W + p.o_M, piv);
         TK_LAUNCH_CHECK("k_qrp_finish");
-        k_form_u<YT, LT><<<cdiv(p.m, 256), 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_M, flag, U, Ulp, ldlp);
+        k_form_u<YT, LT><<<cdiv(p.m * ldlp, 256), 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_M, flag, U, Ulp, ldlp);
         TK_LAUNCH_CHECK("k_form_u");
         // fallback, gated on the flag
         k_house_qrp<YT, LT><<<1, 1024, 0, s>>>(Y, W + p.o_A, I, (int)K, p.R, W + p.o_V, W + p.o_w, W + p.o_beta, perm, flag, 1, U,

@@ -54,6 +54,12 @@ template <typename AT, typename ST>
 __device__ inline AT load_as(const ST* p, int64_t i) {
     return load_as<AT, ST>((const void*)p, i);
 }
+template <typename AT, typename ST>
+__device__ inline AT load_as(const ST* p, uint32_t i) {
+    if constexpr (sizeof(AT) == 8) return ((const double*)p)[i];
+    else if constexpr (sizeof(ST) == 4) return ((const float*)p)[i];
+    else return bf16_to_f32(((const bf16_t*)p)[i]);
+}
 
 // Zero the rows of Y strictly between the previous non-empty row and row s (and, for the last
 // non-empty row, every row after it).  Called by the owner of row s, once per row.
@@ -93,11 +99,25 @@ template <typename AT> struct Vec4;
 template <> struct Vec4<float> { typedef float4 type; };
 template <> struct Vec4<double> { typedef double4 type; };
 
-// Order-3 TTMc on MFMA.  A row segment is consumed in batches of 64 nonzeros: the 64 index pairs
-// and values are read coalesced (one per lane, the next batch prefetched), staged in the wave's
-// LDS slot, and lane group g = l/16 takes nonzeros 16g..16g+15 of the batch; step s of the 16
-// MFMAs contracts nonzeros {16g + s}.  All 32 factor gathers of a batch are issued before its
-// MFMAs.  The last, partial batch of a segment uses 4-nonzero steps (nonzero 4s + g).
+// Order-3 TTMc on MFMA.  A row segment is consumed in batches of 64 nonzeros: the batch's index
+// pairs and values are read coalesced (one per lane; the last batch of a segment is padded with
+// zero values at a valid index) and staged in the wave's LDS slot.  In a full batch lane group
+// g = l/16 takes nonzeros 16g..16g+15 and step s of the 16 MFMAs contracts nonzeros {16g + s}; in
+// the last, partial batch step s contracts nonzeros {4s + g} so that ceil(r/4) steps cover r.
+// All factor gathers of a batch are issued before its MFMAs, and the next batch's stream loads
+// are issued after the gathers (memory counters retire in order, so waiting for the gathers does
+// not wait for the prefetch).
+template <typename AT, typename ST>
+__device__ inline void stage_load(const TtmcArgs& a, const int32_t* __restrict__ ia, const int32_t* __restrict__ ib,
+                                  int p, int end, int lane, int& pa, int& pb, AT& px) {
+    const int q = p + lane;
+    const bool v = q < end;
+    const int qc = v ? q : end - 1;
+    pa = ia[qc];
+    pb = ib[qc];
+    px = v ? load_as<AT, ST>(a.val, qc) : AT(0);
+}
+
 template <typename AT, typename ST>
 __global__ __launch_bounds__(256) void k_ttmc3_mfma(TtmcArgs a) {
     __shared__ __align__(32) int32_t s_ia[4][64];
@@ -113,78 +133,82 @@ __global__ __launch_bounds__(256) void k_ttmc3_mfma(TtmcArgs a) {
     const int slot = a.chunk_slot[ch];
     const int32_t* __restrict__ ia = a.idx;
     const int32_t* __restrict__ ib = a.idx + a.nnz;
-    const ST* __restrict__ Fa = (const ST*)a.F[0] + m;
-    const ST* __restrict__ Fb = (const ST*)a.F[1] + m;
+    // uniform bases with 32-bit per-lane element offsets (global loads with a scalar base)
+    const ST* __restrict__ Fa = (const ST*)a.F[0];
+    const ST* __restrict__ Fb = (const ST*)a.F[1];
     const int Ra = a.R[0], Rb = a.R[1], K = a.K;
     int s = a.chunk_row[ch];
     int q = q0;
+    int pa, pb;
+    AT px;
+    // first batch of the chunk
+    {
+        const int end0 = min(a.ptr[s + 1], q1);
+        stage_load<AT, ST>(a, ia, ib, q, end0, lane, pa, pb, px);
+    }
     while (q < q1) {
         const int rs = a.ptr[s];
         const int end = min(a.ptr[s + 1], q1);
         const bool owner = rs >= q0;
         typename Acc<AT>::type acc = {0, 0, 0, 0};
-        int p = q;
-        const int nfull = (end - p) >> 6;
-        int pa = 0, pb = 0;
-        AT px = AT(0);
-        if (nfull > 0) {
-            pa = ia[p + lane];
-            pb = ib[p + lane];
-            px = load_as<AT, ST>(a.val, p + lane);
-        }
-        for (int b = 0; b < nfull; ++b) {
+        for (int p = q; p < end; p += 64) {
+            const int r = min(64, end - p);
             s_ia[w][lane] = pa;
             s_ib[w][lane] = pb;
             s_x[w][lane] = px;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (b + 1 < nfull) {
-                pa = ia[p + 64 + lane];
-                pb = ib[p + 64 + lane];
-                px = load_as<AT, ST>(a.val, p + 64 + lane);
+            // where the next batch starts: this segment, else the next row of the chunk
+            const int pn = p + 64 < end ? p + 64 : end;
+            const int endn = p + 64 < end ? end : (end < q1 ? min(a.ptr[s + 2], q1) : 0);
+            if (r == 64) {
+                int ja[16], jb[16];
+                AT xs[16];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int4 ta = *(const int4*)&s_ia[w][16 * kq + 4 * v];
+                    const int4 tb = *(const int4*)&s_ib[w][16 * kq + 4 * v];
+                    const typename Vec4<AT>::type tx = *(const typename Vec4<AT>::type*)&s_x[w][16 * kq + 4 * v];
+                    ja[4 * v] = ta.x; ja[4 * v + 1] = ta.y; ja[4 * v + 2] = ta.z; ja[4 * v + 3] = ta.w;
+                    jb[4 * v] = tb.x; jb[4 * v + 1] = tb.y; jb[4 * v + 2] = tb.z; jb[4 * v + 3] = tb.w;
+                    xs[4 * v] = tx.x; xs[4 * v + 1] = tx.y; xs[4 * v + 2] = tx.z; xs[4 * v + 3] = tx.w;
+                }
+                AT av[16], bv[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    av[t] = load_as<AT, ST>(Fa, (uint32_t)(ja[t] * 16 + m));
+                    bv[t] = load_as<AT, ST>(Fb, (uint32_t)(jb[t] * 16 + m));
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if (pn < endn) stage_load<AT, ST>(a, ia, ib, pn, endn, lane, pa, pb, px);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < 16; ++t) acc = Acc<AT>::mfma(av[t] * xs[t], bv[t], acc);
+            } else {
+                const int ngroups = (r + 15) >> 4;   // groups of 4 steps of 4 nonzeros
+                AT av[16], bv[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    if ((t >> 2) < ngroups) {
+                        const int e = 4 * t + kq;
+                        av[t] = load_as<AT, ST>(Fa, (uint32_t)(s_ia[w][e] * 16 + m)) * s_x[w][e];
+                        bv[t] = load_as<AT, ST>(Fb, (uint32_t)(s_ib[w][e] * 16 + m));
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if (pn < endn) stage_load<AT, ST>(a, ia, ib, pn, endn, lane, pa, pb, px);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < 16; ++t)
+                    if ((t >> 2) < ngroups) acc = Acc<AT>::mfma(av[t], bv[t], acc);
             }
-            int ja[16], jb[16];
-            AT xs[16];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int4 ta = *(const int4*)&s_ia[w][16 * kq + 4 * v];
-                const int4 tb = *(const int4*)&s_ib[w][16 * kq + 4 * v];
-                const typename Vec4<AT>::type tx = *(const typename Vec4<AT>::type*)&s_x[w][16 * kq + 4 * v];
-                ja[4 * v] = ta.x; ja[4 * v + 1] = ta.y; ja[4 * v + 2] = ta.z; ja[4 * v + 3] = ta.w;
-                jb[4 * v] = tb.x; jb[4 * v + 1] = tb.y; jb[4 * v + 2] = tb.z; jb[4 * v + 3] = tb.w;
-                xs[4 * v] = tx.x; xs[4 * v + 1] = tx.y; xs[4 * v + 2] = tx.z; xs[4 * v + 3] = tx.w;
-            }
-            AT av[16], bv[16];
-#pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                av[t] = load_as<AT, ST>(Fa, (int64_t)ja[t] * 16);
-                bv[t] = load_as<AT, ST>(Fb, (int64_t)jb[t] * 16);
-            }
-#pragma unroll
-            for (int t = 0; t < 16; ++t) acc = Acc<AT>::mfma(av[t] * xs[t], bv[t], acc);
-            p += 64;
-        }
-        // partial batch: 4-nonzero steps, in groups of 4 steps with their gathers issued first
-        for (; p < end; p += 16) {
-            AT av[4], bv[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int qq = p + 4 * t + kq;
-                const bool valid = qq < end;
-                const int qc = valid ? qq : end - 1;
-                const AT x = valid ? load_as<AT, ST>(a.val, qc) : AT(0);
-                av[t] = load_as<AT, ST>(Fa, (int64_t)ia[qc] * 16) * x;
-                bv[t] = load_as<AT, ST>(Fb, (int64_t)ib[qc] * 16);
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) acc = Acc<AT>::mfma(av[t], bv[t], acc);
         }
         AT* dst = owner ? (AT*)a.Y + (int64_t)a.rows[s] * K : (AT*)a.carry + (int64_t)slot * K;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int r = Acc<AT>::row(kq, v);
-            if (r < Ra && m < Rb) dst[r * Rb + m] = acc[v];
+            const int rr = Acc<AT>::row(kq, v);
+            if (rr < Ra && m < Rb) dst[rr * Rb + m] = acc[v];
         }
         if (owner) zero_gaps<AT>(a, s, lane);
         q = end;
