@@ -58,7 +58,7 @@ void free_ctx(tk_ctx* c) {
     free_events(c);
     for (int m = 0; m < kMaxOrder; ++m) {
         ModeLayout& ml = c->mode[m];
-        void* ps[] = {ml.rows, ml.ptr, ml.idx, ml.val, ml.chunk_ptr, ml.chunk_row, ml.chunk_slot, ml.split};
+        void* ps[] = {ml.rows, ml.ptr, ml.pptr, ml.idx, ml.val, ml.chunk_ptr, ml.chunk_row, ml.chunk_slot, ml.split};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (c->Ulp[m]) (void)hipFree(c->Ulp[m]);
@@ -196,10 +196,7 @@ int tucker_get_csf(tk_ctx* ctx, int mode, int32_t* rows, int64_t* ptr, int32_t* 
     TK_HIP(hipStreamSynchronize(s));
     for (size_t i = 0; i < h32.size(); ++i) h64[i] = h32[i];
     TK_HIP(hipMemcpyAsync(ptr, h64.data(), h64.size() * 8, hipMemcpyHostToDevice, s));
-    if (ctx->nnz > 0) {
-        TK_HIP(hipMemcpyAsync(idx, ml.idx, (size_t)ctx->nnz * 4 * (ctx->N - 1), hipMemcpyDeviceToDevice, s));
-        TK_HIP(hipMemcpyAsync(vals, ml.val, (size_t)ctx->nnz * dtype_size(ctx->dtype), hipMemcpyDeviceToDevice, s));
-    }
+    if (ctx->nnz > 0 && (st = export_layout(ctx, mode, idx, vals, s))) return st;
     TK_HIP(hipStreamSynchronize(s));
     ctx->last_stream = s;
     return TK_OK;

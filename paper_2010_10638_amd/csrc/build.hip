@@ -143,6 +143,33 @@ __global__ void k_gather_mode(const int32_t* __restrict__ perm, int64_t D,
     val[q] = store_val<ST>(dvals[src]);
 }
 
+// Scatter the sorted entry q (row s = the number of row heads up to q, minus one) to its padded
+// slot pptr[s] + (q - ptr[s]); the first entry of a row gets the kFirstOfRow flag on idx[0].
+template <typename ST>
+__global__ void k_pad_scatter(const int32_t* __restrict__ h, const int32_t* __restrict__ pos, int64_t D,
+                              const int32_t* __restrict__ ptr, const int32_t* __restrict__ pptr, int nothers,
+                              const int32_t* __restrict__ idx_u, const ST* __restrict__ val_u, int64_t P,
+                              int32_t* __restrict__ idx_p, ST* __restrict__ val_p) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= D) return;
+    const int64_t s = pos[q] - (h[q] ? 0 : 1);
+    const int64_t d = pptr[s] + (q - ptr[s]);
+    for (int j = 0; j < nothers; ++j) {
+        int32_t v = idx_u[(int64_t)j * D + q];
+        if (j == 0 && h[q]) v = (int32_t)((uint32_t)v | kFirstOfRow);
+        idx_p[(int64_t)j * P + d] = v;
+    }
+    val_p[d] = val_u[q];
+}
+
+template <typename ST>
+__global__ void k_pad_fill(int nothers, int64_t P, int32_t* __restrict__ idx_p, ST* __restrict__ val_p) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P) return;
+    for (int j = 0; j < nothers; ++j) idx_p[(int64_t)j * P + e] = 0;
+    val_p[e] = ST(0);
+}
+
 __global__ void k_rows(const int32_t* __restrict__ h, const int32_t* __restrict__ pos,
                        const int32_t* __restrict__ rowid, int64_t D, int64_t S,
                        int32_t* __restrict__ rows, int32_t* __restrict__ ptr) {
@@ -173,9 +200,9 @@ int launch_gather(const int32_t* perm, int64_t D, const int32_t* rowsrc, const G
     return TK_OK;
 }
 
-// Greedy chunking: whole rows are packed into chunks of at most L nonzeros; a row longer than
-// L is cut into pieces of L, and every piece after the first is a carrier whose partial row
-// sum goes to a carry slot and is added by the fix-up pass.
+// Greedy chunking of the padded stream: whole rows are packed into chunks of at most L entries; a
+// row longer than L is cut into pieces of L (L a multiple of 64), and every piece after the first
+// is a carrier whose partial row sum goes to a carry slot and is added by the fix-up pass.
 void make_chunks(const std::vector<int32_t>& ptr, int64_t L, std::vector<int32_t>& cptr,
                  std::vector<int32_t>& crow, std::vector<int32_t>& cslot,
                  std::vector<int32_t>& split, int64_t& ncarry, int32_t& maxrow) {
@@ -228,7 +255,45 @@ int upload(T** dst, const std::vector<T>& v, hipStream_t s) {
     return TK_OK;
 }
 
+// Padded entry e -> its unpadded position (row found by binary search of pptr); pads are skipped
+// and the row flag is masked off.
+template <typename ST>
+__global__ void k_export(const int32_t* __restrict__ ptr, const int32_t* __restrict__ pptr, int64_t S, int64_t P,
+                         int64_t D, int nothers, const int32_t* __restrict__ idx_p, const ST* __restrict__ val_p,
+                         int32_t* __restrict__ idx_out, ST* __restrict__ val_out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P) return;
+    int64_t lo = 0, hi = S;  // largest s with pptr[s] <= e
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (pptr[mid] <= e) lo = mid; else hi = mid;
+    }
+    const int64_t off = e - pptr[lo];
+    if (off >= (int64_t)ptr[lo + 1] - ptr[lo]) return;
+    const int64_t d = ptr[lo] + off;
+    for (int j = 0; j < nothers; ++j) idx_out[(int64_t)j * D + d] = idx_p[(int64_t)j * P + e] & kIndexMask;
+    val_out[d] = val_p[e];
+}
+
 }  // namespace
+
+int export_layout(tk_ctx* ctx, int mode, int32_t* idx_out, void* val_out, hipStream_t s) {
+    const ModeLayout& ml = ctx->mode[mode];
+    if (ml.P == 0) return TK_OK;
+    const unsigned g = blocks_for(ml.P);
+    const int no = ctx->N - 1;
+    if (ctx->dtype == TK_F64)
+        k_export<double><<<g, 256, 0, s>>>(ml.ptr, ml.pptr, ml.S, ml.P, ctx->nnz, no, ml.idx, (const double*)ml.val,
+                                           idx_out, (double*)val_out);
+    else if (ctx->dtype == TK_F32)
+        k_export<float><<<g, 256, 0, s>>>(ml.ptr, ml.pptr, ml.S, ml.P, ctx->nnz, no, ml.idx, (const float*)ml.val,
+                                          idx_out, (float*)val_out);
+    else
+        k_export<bf16_t><<<g, 256, 0, s>>>(ml.ptr, ml.pptr, ml.S, ml.P, ctx->nnz, no, ml.idx, (const bf16_t*)ml.val,
+                                           idx_out, (bf16_t*)val_out);
+    TK_LAUNCH_CHECK("k_export");
+    return TK_OK;
+}
 
 int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t n, hipStream_t s) {
     const int N = ctx->N;
@@ -294,7 +359,7 @@ int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t
 
     // 3. per mode: sort by the mode key, gather the SoA layout, row pointers, chunk table
     const int32_t* dc = (const int32_t*)dco.p;
-    const int64_t L = std::min<int64_t>(2048, std::max<int64_t>(64, (D / 8192 + 3) / 4 * 4));
+    const int64_t L = std::min<int64_t>(2048, std::max<int64_t>(64, (D / 8192 + 63) / 64 * 64));
     for (int m = 0; m < N; ++m) {
         ModeLayout& ml = ctx->mode[m];
         int no = 0;
@@ -315,13 +380,16 @@ int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t
         for (int j = 0; j < no; ++j) ml.K *= ctx->ranks[ml.others[j]];
 
         size_t vs = dtype_size(ctx->dtype);
-        TK_HIP(hipMalloc((void**)&ml.idx, dd * 4 * (N - 1)));
-        TK_HIP(hipMalloc(&ml.val, dd * vs));
         if (D == 0) {
             ml.S = 0;
+            ml.P = 0;
+            TK_HIP(hipMalloc((void**)&ml.idx, 16 * (N - 1)));
+            TK_HIP(hipMalloc(&ml.val, 16));
             TK_HIP(hipMalloc((void**)&ml.rows, 16));
             TK_HIP(hipMalloc((void**)&ml.ptr, 16));
+            TK_HIP(hipMalloc((void**)&ml.pptr, 16));
             TK_HIP(hipMemsetAsync(ml.ptr, 0, 4, s));
+            TK_HIP(hipMemsetAsync(ml.pptr, 0, 4, s));
             ml.nchunks = 0;
             std::vector<int32_t> z{0};
             if ((st = upload(&ml.chunk_ptr, z, s))) return st;
@@ -344,12 +412,14 @@ int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t
         g.nothers = no;
         for (int j = 0; j < no; ++j) g.other[j] = dc + (int64_t)ml.others[j] * D;
         const int32_t* rowsrc = dc + (int64_t)m * D;
+        DevBuf idx_u, val_u;
+        if ((st = dalloc(idx_u, dd * 4 * (N - 1))) || (st = dalloc(val_u, dd * vs))) return st;
         if (ctx->dtype == TK_F64)
-            st = launch_gather<double>((int32_t*)iout.p, D, rowsrc, g, (double*)dva.p, (int32_t*)rowid.p, ml.idx, ml.val, s);
+            st = launch_gather<double>((int32_t*)iout.p, D, rowsrc, g, (double*)dva.p, (int32_t*)rowid.p, (int32_t*)idx_u.p, val_u.p, s);
         else if (ctx->dtype == TK_F32)
-            st = launch_gather<float>((int32_t*)iout.p, D, rowsrc, g, (double*)dva.p, (int32_t*)rowid.p, ml.idx, ml.val, s);
+            st = launch_gather<float>((int32_t*)iout.p, D, rowsrc, g, (double*)dva.p, (int32_t*)rowid.p, (int32_t*)idx_u.p, val_u.p, s);
         else
-            st = launch_gather<bf16_t>((int32_t*)iout.p, D, rowsrc, g, (double*)dva.p, (int32_t*)rowid.p, ml.idx, ml.val, s);
+            st = launch_gather<bf16_t>((int32_t*)iout.p, D, rowsrc, g, (double*)dva.p, (int32_t*)rowid.p, (int32_t*)idx_u.p, val_u.p, s);
         if (st) return st;
         k_heads32<<<blocks_for(D), 256, 0, s>>>((int32_t*)rowid.p, D, (int32_t*)hbuf.p);
         TK_LAUNCH_CHECK("k_heads32");
@@ -368,8 +438,37 @@ int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t
         std::vector<int32_t> hptr((size_t)ml.S + 1);
         TK_HIP(hipMemcpyAsync(hptr.data(), ml.ptr, hptr.size() * 4, hipMemcpyDeviceToHost, s));
         TK_HIP(hipStreamSynchronize(s));
+        std::vector<int32_t> hpptr((size_t)ml.S + 1);
+        hpptr[0] = 0;
+        for (int64_t r = 0; r < ml.S; ++r) {
+            const int64_t len = (int64_t)hptr[r + 1] - hptr[r];
+            const int64_t padded = (int64_t)hpptr[r] + (len + 3) / 4 * 4;
+            if (padded >= ((int64_t)1 << 31)) return set_error(TK_ERR_UNSUPPORTED, "padded stream exceeds 2^31 entries");
+            hpptr[r + 1] = (int32_t)padded;
+        }
+        ml.P = hpptr[ml.S];
+        if ((st = upload(&ml.pptr, hpptr, s))) return st;
+        TK_HIP(hipMalloc((void**)&ml.idx, (size_t)ml.P * 4 * (N - 1)));
+        TK_HIP(hipMalloc(&ml.val, (size_t)ml.P * vs));
+        {
+            const unsigned gp = blocks_for(ml.P), gd = blocks_for(D);
+            if (ctx->dtype == TK_F64) {
+                k_pad_fill<double><<<gp, 256, 0, s>>>(N - 1, ml.P, ml.idx, (double*)ml.val);
+                k_pad_scatter<double><<<gd, 256, 0, s>>>((int32_t*)hbuf.p, (int32_t*)pbuf.p, D, ml.ptr, ml.pptr, N - 1,
+                                                         (int32_t*)idx_u.p, (const double*)val_u.p, ml.P, ml.idx, (double*)ml.val);
+            } else if (ctx->dtype == TK_F32) {
+                k_pad_fill<float><<<gp, 256, 0, s>>>(N - 1, ml.P, ml.idx, (float*)ml.val);
+                k_pad_scatter<float><<<gd, 256, 0, s>>>((int32_t*)hbuf.p, (int32_t*)pbuf.p, D, ml.ptr, ml.pptr, N - 1,
+                                                        (int32_t*)idx_u.p, (const float*)val_u.p, ml.P, ml.idx, (float*)ml.val);
+            } else {
+                k_pad_fill<bf16_t><<<gp, 256, 0, s>>>(N - 1, ml.P, ml.idx, (bf16_t*)ml.val);
+                k_pad_scatter<bf16_t><<<gd, 256, 0, s>>>((int32_t*)hbuf.p, (int32_t*)pbuf.p, D, ml.ptr, ml.pptr, N - 1,
+                                                         (int32_t*)idx_u.p, (const bf16_t*)val_u.p, ml.P, ml.idx, (bf16_t*)ml.val);
+            }
+            TK_LAUNCH_CHECK("k_pad_scatter");
+        }
         std::vector<int32_t> cptr, crow, cslot, split;
-        make_chunks(hptr, L, cptr, crow, cslot, split, ml.ncarry, ml.max_row_nnz);
+        make_chunks(hpptr, L, cptr, crow, cslot, split, ml.ncarry, ml.max_row_nnz);
         ml.nchunks = (int64_t)crow.size();
         ml.nsplit = (int64_t)split.size() / 3;
         if ((st = upload(&ml.chunk_ptr, cptr, s)) || (st = upload(&ml.chunk_row, crow, s)) ||

@@ -48,18 +48,27 @@ inline size_t dtype_size(int dt) { return dt == TK_F64 ? 8 : (dt == TK_F32 ? 4 :
 inline size_t ytype_size(int dt) { return dt == TK_F64 ? 8 : 4; }
 
 // Per-mode sorted layout and the chunk walk of the TTMc kernels.
+// The sorted nonzeros of a mode are stored padded: row s occupies [pptr[s], pptr[s+1]), its
+// ptr[s+1]-ptr[s] nonzeros followed by zero-valued entries (index 0) up to a multiple of 4, so that
+// a 4-nonzero MFMA step never spans two rows.  Bit 31 of the first other-mode index marks the first
+// entry of every row (kFirstOfRow); readers mask it off.
+constexpr uint32_t kFirstOfRow = 0x80000000u;
+constexpr int32_t kIndexMask = 0x7fffffff;
+
 struct ModeLayout {
     int64_t S = 0;                  // distinct i_n
     int32_t* rows = nullptr;        // [S]      distinct i_n, ascending
-    int32_t* ptr = nullptr;         // [S + 1]  row pointers
-    int32_t* idx = nullptr;         // [(N-1) * nnz] other-mode indices, modes ascending, SoA
-    void* val = nullptr;            // [nnz] TTMc storage type
+    int32_t* ptr = nullptr;         // [S + 1]  row pointers into the unpadded order
+    int32_t* pptr = nullptr;        // [S + 1]  row pointers into the padded stream (multiples of 4)
+    int64_t P = 0;                  // padded stream length
+    int32_t* idx = nullptr;         // [(N-1) * P] other-mode indices, modes ascending, SoA (padded)
+    void* val = nullptr;            // [P] TTMc storage type (padded)
     int64_t K = 0;                  // prod_{t != n} R_t
     int others[kMaxOrder - 1];      // other modes, ascending
     int fiber_slot = -1;            // position of the fiber mode in others (order >= 4), else -1
     // chunk walk
     int64_t nchunks = 0;
-    int32_t* chunk_ptr = nullptr;   // [nchunks + 1] first nonzero of each chunk
+    int32_t* chunk_ptr = nullptr;   // [nchunks + 1] first padded entry of each chunk (multiples of 4)
     int32_t* chunk_row = nullptr;   // [nchunks] compressed row holding the chunk's first nonzero
     int32_t* chunk_slot = nullptr;  // [nchunks] carry slot of a chunk that starts inside a row, else -1
     int64_t ncarry = 0;             // number of carry slots
@@ -124,6 +133,8 @@ int hip_error(hipError_t e, const char* what);
 // Layout builder (build.hip)
 int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t nnz_in,
                  hipStream_t s);
+// unpadded, flag-free copy of one mode's indices and values (tucker_get_csf)
+int export_layout(tk_ctx* ctx, int mode, int32_t* idx_out, void* val_out, hipStream_t s);
 
 // Conversions (core.hip)
 int convert_factor(tk_ctx* ctx, int k, const double* U, hipStream_t s);

@@ -25,12 +25,12 @@ struct TtmcArgs {
     const int32_t* chunk_row;
     const int32_t* chunk_slot;
     int32_t nchunks;
-    const int32_t* ptr;
+    const int32_t* ptr;       // padded row pointers
     const int32_t* rows;
     int32_t S;
     int32_t In;
-    const int32_t* idx;       // [nm1][nnz]
-    int64_t nnz;
+    const int32_t* idx;       // [nm1][nnz] padded stream; bit 31 of idx[0] flags the first entry of a row
+    int64_t nnz;              // padded stream length
     const void* val;
     const void* F[kMaxOrder - 1];
     int32_t ld[kMaxOrder - 1];
@@ -113,7 +113,7 @@ __device__ inline void stage_load(const TtmcArgs& a, const int32_t* __restrict__
     const int q = p + lane;
     const bool v = q < end;
     const int qc = v ? q : end - 1;
-    pa = ia[qc];
+    pa = ia[qc] & kIndexMask;
     pb = ib[qc];
     px = v ? load_as<AT, ST>(a.val, qc) : AT(0);
 }
@@ -216,6 +216,117 @@ __global__ __launch_bounds__(256) void k_ttmc3_mfma(TtmcArgs a) {
     }
 }
 
+// Order-3 TTMc (R_a, R_b <= 16) on FP32 MFMA for FP32 or BF16 storage, walking the padded stream
+// of a chunk in batches of 64 entries regardless of row boundaries (rows are padded to whole
+// 4-entry steps).  Per batch:
+//   1. the 64 index pairs and values (read coalesced during the previous batch) are staged in the
+//      wave's LDS slot; a ballot of the row flags marks the steps that open a new row;
+//   2. the 64 + 64 factor rows are fetched straight into LDS with 16-byte global->LDS loads
+//      (4 instructions per factor for FP32 rows of 64 B, 2 for BF16 rows of 32 B);
+//   3. the next batch's stream loads are issued, then the wave waits for the row fetches only;
+//   4. step t contracts entries 4t..4t+3 (lane l carries entry 4t + l/16 and factor column l%16)
+//      with v_mfma_f32_16x16x4f32; a flagged step first writes out the finished row.
+template <typename ST>
+__global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
+    constexpr int ROWB = 16 * (int)sizeof(ST);   // bytes of one padded factor row
+    constexpr int LPR = ROWB / 16;               // lanes per row in a 16-byte fetch
+    constexpr int RPI = 64 / LPR;                // rows per fetch instruction
+    constexpr int NI = 64 / RPI;                 // fetch instructions per factor per batch
+    __shared__ __align__(16) ST sA[4][64 * 16];
+    __shared__ __align__(16) ST sB[4][64 * 16];
+    __shared__ __align__(16) int32_t s_ia[4][64];
+    __shared__ __align__(16) int32_t s_ib[4][64];
+    __shared__ __align__(16) float s_x[4][64];    // entry n at (n % 4) * 16 + n / 4
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int ch = blockIdx.x * 4 + w;
+    if (ch >= a.nchunks) return;
+    const int kq = lane >> 4, m = lane & 15;
+    const int q0 = a.chunk_ptr[ch], q1 = a.chunk_ptr[ch + 1];
+    const int slot = a.chunk_slot[ch];
+    const int32_t* __restrict__ ia = a.idx;
+    const int32_t* __restrict__ ib = a.idx + a.nnz;
+    const char* __restrict__ Fa = (const char*)a.F[0];
+    const char* __restrict__ Fb = (const char*)a.F[1];
+    const int Ra = a.R[0], Rb = a.R[1], K = a.K;
+    int s = a.chunk_row[ch];
+    f4_t acc = {0, 0, 0, 0};
+
+    auto flush = [&](int row) {
+        const bool owner = a.ptr[row] >= q0;
+        float* dst = owner ? (float*)a.Y + (int64_t)a.rows[row] * K : (float*)a.carry + (int64_t)slot * K;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 4 * kq + v;
+            if (r < Ra && m < Rb) dst[r * Rb + m] = acc[v];
+        }
+        if (owner) zero_gaps<float>(a, row, lane);
+    };
+
+    int pa, pb;
+    float px;
+    {
+        const int qq = q0 + lane;
+        const bool v = qq < q1;
+        pa = v ? ia[qq] : 0;
+        pb = v ? ib[qq] : 0;
+        px = v ? load_as<float, ST>(a.val, qq) : 0.f;
+    }
+    for (int p = q0; p < q1; p += 64) {
+        const int nsteps = min(16, (q1 - p) >> 2);
+        const uint64_t starts = __ballot(pa < 0);
+        s_ia[w][lane] = pa & kIndexMask;
+        s_ib[w][lane] = pb;
+        s_x[w][(lane & 3) * 16 + (lane >> 2)] = px;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+            const int row = j * RPI + lane / LPR;
+            const int part = (lane % LPR) * 16;
+            const char* ga = Fa + (size_t)(uint32_t)s_ia[w][row] * ROWB + part;
+            const char* gb = Fb + (size_t)(uint32_t)s_ib[w][row] * ROWB + part;
+            __builtin_amdgcn_global_load_lds((const void*)ga, (__attribute__((address_space(3))) void*)&sA[w][j * RPI * 16], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)gb, (__attribute__((address_space(3))) void*)&sB[w][j * RPI * 16], 16, 0, 0);
+        }
+        const bool more = p + 64 < q1;
+        if (more) {
+            const int qq = p + 64 + lane;
+            const bool v = qq < q1;
+            pa = v ? ia[qq] : 0;
+            pb = v ? ib[qq] : 0;
+            px = v ? load_as<float, ST>(a.val, qq) : 0.f;
+            __builtin_amdgcn_s_waitcnt(0x0F73);   // vmcnt <= 3: the row fetches are done, the 3 stream loads may fly
+        } else {
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt = 0
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float xs[16];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float4 t4 = *(const float4*)&s_x[w][kq * 16 + 4 * v];
+            xs[4 * v] = t4.x; xs[4 * v + 1] = t4.y; xs[4 * v + 2] = t4.z; xs[4 * v + 3] = t4.w;
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            if (t < nsteps) {
+                if (((starts >> (4 * t)) & 1ull) && (p + 4 * t != q0)) {
+                    flush(s);
+                    ++s;
+                    acc = f4_t{0, 0, 0, 0};
+                }
+                const int e = (4 * t + kq) * 16 + m;
+                float av, bv;
+                if constexpr (sizeof(ST) == 4) { av = sA[w][e]; bv = sB[w][e]; }
+                else { av = bf16_to_f32(sA[w][e]); bv = bf16_to_f32(sB[w][e]); }
+                acc = Acc<float>::mfma(av * xs[t], bv, acc);
+            }
+        }
+    }
+    flush(s);
+}
+
 template <typename AT, typename ST, int KPL>
 __global__ __launch_bounds__(256) void k_ttmc_generic(TtmcArgs a) {
     extern __shared__ uint16_t dig[];  // [K][nm1]: digit of each other mode for column c
@@ -247,7 +358,7 @@ __global__ __launch_bounds__(256) void k_ttmc_generic(TtmcArgs a) {
             int64_t base[kMaxOrder - 1];
 #pragma unroll
             for (int t = 0; t < kMaxOrder - 1; ++t)
-                base[t] = (t < nm1) ? (int64_t)a.idx[(int64_t)t * a.nnz + p] * a.ld[t] : 0;
+                base[t] = (t < nm1) ? (int64_t)(a.idx[(int64_t)t * a.nnz + p] & kIndexMask) * a.ld[t] : 0;
 #pragma unroll
             for (int j = 0; j < KPL; ++j) {
                 const int c = lane + 64 * j;
@@ -319,12 +430,12 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s) {
     a.chunk_row = ml.chunk_row;
     a.chunk_slot = ml.chunk_slot;
     a.nchunks = (int32_t)ml.nchunks;
-    a.ptr = ml.ptr;
+    a.ptr = ml.pptr;
     a.rows = ml.rows;
     a.S = (int32_t)ml.S;
     a.In = (int32_t)In;
     a.idx = ml.idx;
-    a.nnz = ctx->nnz;
+    a.nnz = ml.P;
     a.val = ml.val;
     a.nm1 = N - 1;
     a.K = (int32_t)ml.K;
@@ -341,10 +452,16 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s) {
     const unsigned grid = (unsigned)((ml.nchunks + 3) / 4);
     int st = TK_OK;
     if (mfma_ok) {
-        if (ctx->dtype == TK_F64) k_ttmc3_mfma<double, double><<<grid, 256, 0, s>>>(a);
-        else if (ctx->dtype == TK_F32) k_ttmc3_mfma<float, float><<<grid, 256, 0, s>>>(a);
-        else k_ttmc3_mfma<float, bf16_t><<<grid, 256, 0, s>>>(a);
-        TK_LAUNCH_CHECK("k_ttmc3_mfma");
+        if (ctx->dtype == TK_F64) {
+            k_ttmc3_mfma<double, double><<<grid, 256, 0, s>>>(a);
+            TK_LAUNCH_CHECK("k_ttmc3_mfma");
+        } else if (ctx->dtype == TK_F32) {
+            k_ttmc3_lds<float><<<grid, 256, 0, s>>>(a);
+            TK_LAUNCH_CHECK("k_ttmc3_lds");
+        } else {
+            k_ttmc3_lds<bf16_t><<<grid, 256, 0, s>>>(a);
+            TK_LAUNCH_CHECK("k_ttmc3_lds");
+        }
     } else {
         if (ctx->dtype == TK_F64) st = launch_generic<double, double>(a, s);
         else if (ctx->dtype == TK_F32) st = launch_generic<float, float>(a, s);
