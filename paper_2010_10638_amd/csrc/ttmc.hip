@@ -61,13 +61,19 @@ __device__ inline AT load_as(const ST* p, uint32_t i) {
     else return bf16_to_f32(((const bf16_t*)p)[i]);
 }
 
+// Read-only layout arrays indexed by a wave-uniform value: reading through the constant address
+// space lets the compiler use scalar loads (tracked apart from the vector-memory counter).
+__device__ inline int32_t ld_const(const int32_t* p, int64_t i) {
+    return ((const __attribute__((address_space(4))) int32_t*)p)[i];
+}
+
 // Zero the rows of Y strictly between the previous non-empty row and row s (and, for the last
 // non-empty row, every row after it).  Called by the owner of row s, once per row.
 template <typename AT>
 __device__ inline void zero_gaps(const TtmcArgs& a, int s, int lane) {
     AT* Y = (AT*)a.Y;
-    int g0 = (s == 0) ? 0 : a.rows[s - 1] + 1;
-    int g1 = a.rows[s];
+    int g0 = (s == 0) ? 0 : ld_const(a.rows, s - 1) + 1;
+    int g1 = ld_const(a.rows, s);
     int64_t K = a.K;
     for (int64_t e = (int64_t)g0 * K + lane; e < (int64_t)g1 * K; e += 64) Y[e] = AT(0);
     if (s == a.S - 1)
@@ -124,7 +130,7 @@ __global__ __launch_bounds__(256) void k_ttmc3_mfma(TtmcArgs a) {
     __shared__ __align__(32) int32_t s_ib[4][64];
     __shared__ __align__(32) AT s_x[4][64];
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int ch = blockIdx.x * 4 + w;
     if (ch >= a.nchunks) return;
     const int kq = lane >> 4;         // lane group: which nonzeros of a step this lane carries
@@ -218,29 +224,38 @@ __global__ __launch_bounds__(256) void k_ttmc3_mfma(TtmcArgs a) {
 
 // Order-3 TTMc (R_a, R_b <= 16) on FP32 MFMA for FP32 or BF16 storage, walking the padded stream
 // of a chunk in batches of 64 entries regardless of row boundaries (rows are padded to whole
-// 4-entry steps).  Per batch:
-//   1. the 64 index pairs and values (read coalesced during the previous batch) are staged in the
-//      wave's LDS slot; a ballot of the row flags marks the steps that open a new row;
-//   2. the 64 + 64 factor rows are fetched straight into LDS with 16-byte global->LDS loads
-//      (4 instructions per factor for FP32 rows of 64 B, 2 for BF16 rows of 32 B);
-//   3. the next batch's stream loads are issued, then the wave waits for the row fetches only;
-//   4. step t contracts entries 4t..4t+3 (lane l carries entry 4t + l/16 and factor column l%16)
-//      with v_mfma_f32_16x16x4f32; a flagged step first writes out the finished row.
+// 4-entry steps).  Software pipeline per wave, iteration b:
+//   1. read batch b's factor rows (from the wave's LDS tile) and values into registers;
+//   2. stage batch b+1's index pairs and values (loaded two iterations earlier) in LDS and gather
+//      its 64 + 64 factor rows into registers with 16-byte loads (4 lanes per FP32 row of 64 B,
+//      2 per BF16 row of 32 B), then issue the stream loads of batch b+3;
+//   3. run batch b's 16 MFMA steps - the gathers are in flight meanwhile;
+//   4. write batch b+1's rows into the LDS tile (waiting only for the gathers: memory counters
+//      retire in order and the later stream loads may stay in flight).
+// Step t contracts entries 4t..4t+3 (lane l carries entry 4t + l/16 and factor column l%16) with
+// v_mfma_f32_16x16x4f32; a step whose first entry carries the row flag first writes out the
+// finished row.
+template <typename ST>
+struct LdsTiles {
+    ST A[64 * 16];
+    ST B[64 * 16];
+    float x[2][64];      // entry n at (n % 4) * 16 + n / 4
+    int32_t ia[64];
+    int32_t ib[64];
+};
+
 template <typename ST>
 __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
     constexpr int ROWB = 16 * (int)sizeof(ST);   // bytes of one padded factor row
-    constexpr int LPR = ROWB / 16;               // lanes per row in a 16-byte fetch
-    constexpr int RPI = 64 / LPR;                // rows per fetch instruction
-    constexpr int NI = 64 / RPI;                 // fetch instructions per factor per batch
-    __shared__ __align__(16) ST sA[4][64 * 16];
-    __shared__ __align__(16) ST sB[4][64 * 16];
-    __shared__ __align__(16) int32_t s_ia[4][64];
-    __shared__ __align__(16) int32_t s_ib[4][64];
-    __shared__ __align__(16) float s_x[4][64];    // entry n at (n % 4) * 16 + n / 4
+    constexpr int LPR = ROWB / 16;               // lanes per row in a 16-byte gather
+    constexpr int RPI = 64 / LPR;                // rows per gather instruction
+    constexpr int NI = 64 / RPI;                 // gather instructions per factor per batch
+    __shared__ __align__(16) LdsTiles<ST> tiles[4];
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int ch = blockIdx.x * 4 + w;
     if (ch >= a.nchunks) return;
+    LdsTiles<ST>& T = tiles[w];
     const int kq = lane >> 4, m = lane & 15;
     const int q0 = a.chunk_ptr[ch], q1 = a.chunk_ptr[ch + 1];
     const int slot = a.chunk_slot[ch];
@@ -249,12 +264,14 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
     const char* __restrict__ Fa = (const char*)a.F[0];
     const char* __restrict__ Fb = (const char*)a.F[1];
     const int Ra = a.R[0], Rb = a.R[1], K = a.K;
-    int s = a.chunk_row[ch];
+    const int s0 = a.chunk_row[ch];
+    int s = s0;
     f4_t acc = {0, 0, 0, 0};
 
+    // the chunk owns every row it holds except a first row that started in an earlier chunk
     auto flush = [&](int row) {
-        const bool owner = a.ptr[row] >= q0;
-        float* dst = owner ? (float*)a.Y + (int64_t)a.rows[row] * K : (float*)a.carry + (int64_t)slot * K;
+        const bool owner = (row != s0) || (slot < 0);
+        float* dst = owner ? (float*)a.Y + (int64_t)ld_const(a.rows, row) * K : (float*)a.carry + (int64_t)slot * K;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = 4 * kq + v;
@@ -262,69 +279,107 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
         }
         if (owner) zero_gaps<float>(a, row, lane);
     };
-
-    int pa, pb;
-    float px;
-    {
-        const int qq = q0 + lane;
+    auto stream_load = [&](int pstart, int& ra, int& rb, float& rx) {
+        const int qq = pstart + lane;
         const bool v = qq < q1;
-        pa = v ? ia[qq] : 0;
-        pb = v ? ib[qq] : 0;
-        px = v ? load_as<float, ST>(a.val, qq) : 0.f;
-    }
-    for (int p = q0; p < q1; p += 64) {
-        const int nsteps = min(16, (q1 - p) >> 2);
-        const uint64_t starts = __ballot(pa < 0);
-        s_ia[w][lane] = pa & kIndexMask;
-        s_ib[w][lane] = pb;
-        s_x[w][(lane & 3) * 16 + (lane >> 2)] = px;
+        ra = v ? ia[qq] : 0;
+        rb = v ? ib[qq] : 0;
+        rx = v ? load_as<float, ST>(a.val, qq) : 0.f;
+    };
+    auto stage = [&](int xb, int ra, int rb, float rx) -> uint64_t {
+        const uint64_t st = __ballot(ra < 0);
+        T.ia[lane] = ra & kIndexMask;
+        T.ib[lane] = rb;
+        T.x[xb][(lane & 3) * 16 + (lane >> 2)] = rx;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        return st;
+    };
+    // gathered rows of one batch, in named registers (16 bytes of a factor-A and a factor-B row
+    // per lane and instruction; NI <= 4)
+    static_assert(NI <= 4, "gather registers");
+#define TK_G1(j, va, vb)                                                                            \
+    if constexpr (NI > j) {                                                                         \
+        const int row = j * RPI + lane / LPR;                                                       \
+        const uint32_t part = (uint32_t)(lane % LPR) * 16u;                                         \
+        va = *(const uint4*)(Fa + ((uint32_t)T.ia[row] * (uint32_t)ROWB + part));                   \
+        vb = *(const uint4*)(Fb + ((uint32_t)T.ib[row] * (uint32_t)ROWB + part));                   \
+    }
+#define TK_P1(j, va, vb)                                                                            \
+    if constexpr (NI > j) {                                                                         \
+        *(uint4*)((char*)T.A + j * 1024 + lane * 16) = va;                                          \
+        *(uint4*)((char*)T.B + j * 1024 + lane * 16) = vb;                                          \
+    }
+#define TK_GATHER()                                                                                 \
+    TK_G1(0, ga0, gb0) TK_G1(1, ga1, gb1) TK_G1(2, ga2, gb2) TK_G1(3, ga3, gb3)
+#define TK_PUT()                                                                                    \
+    TK_P1(0, ga0, gb0) TK_P1(1, ga1, gb1) TK_P1(2, ga2, gb2) TK_P1(3, ga3, gb3)                     \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");                                          \
+    __builtin_amdgcn_wave_barrier();                                                                \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint4 ga0, ga1, ga2, ga3, gb0, gb1, gb2, gb3;
+
+    // prologue: batch 0 staged and its rows in LDS; stream registers for batches 1 and 2
+    int r1a = 0, r1b = 0, r2a = 0, r2b = 0;
+    float r1x = 0.f, r2x = 0.f;
+    uint64_t starts;
+    {
+        int r0a, r0b;
+        float r0x;
+        stream_load(q0, r0a, r0b, r0x);
+        if (q0 + 64 < q1) stream_load(q0 + 64, r1a, r1b, r1x);
+        if (q0 + 128 < q1) stream_load(q0 + 128, r2a, r2b, r2x);
+        starts = stage(0, r0a, r0b, r0x);
+        TK_GATHER()
+        TK_PUT()
+    }
+    int xb = 0;
+    for (int p = q0; p < q1; p += 64) {
+        const int nsteps = min(16, (q1 - p) >> 2);
+        const bool plain = starts == 0 || (starts == 1ull && p == q0);   // no row opens inside
+        // 1. stage batch b+1 (past the chunk end: zero values at row 0), gather its rows, then the
+        //    stream loads of batch b+3; the gathers fly while batch b runs
+        const uint64_t starts_next = stage(xb ^ 1, r1a, r1b, r1x);
+        TK_GATHER()
+        r1a = r2a; r1b = r2b; r1x = r2x;
+        if (p + 192 < q1) stream_load(p + 192, r2a, r2b, r2x);
+        // 2. batch b's MFMA steps from the LDS tile
+        auto operand = [&](int t, float& av, float& bv) {
+            const int e = (4 * t + kq) * 16 + m;
+            if constexpr (sizeof(ST) == 4) { av = T.A[e]; bv = T.B[e]; }
+            else { av = bf16_to_f32(T.A[e]); bv = bf16_to_f32(T.B[e]); }
+            av *= T.x[xb][kq * 16 + t];
+        };
+        if (plain) {
+            float av[16], bv[16];
 #pragma unroll
-        for (int j = 0; j < NI; ++j) {
-            const int row = j * RPI + lane / LPR;
-            const int part = (lane % LPR) * 16;
-            const char* ga = Fa + (size_t)(uint32_t)s_ia[w][row] * ROWB + part;
-            const char* gb = Fb + (size_t)(uint32_t)s_ib[w][row] * ROWB + part;
-            __builtin_amdgcn_global_load_lds((const void*)ga, (__attribute__((address_space(3))) void*)&sA[w][j * RPI * 16], 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((const void*)gb, (__attribute__((address_space(3))) void*)&sB[w][j * RPI * 16], 16, 0, 0);
-        }
-        const bool more = p + 64 < q1;
-        if (more) {
-            const int qq = p + 64 + lane;
-            const bool v = qq < q1;
-            pa = v ? ia[qq] : 0;
-            pb = v ? ib[qq] : 0;
-            px = v ? load_as<float, ST>(a.val, qq) : 0.f;
-            __builtin_amdgcn_s_waitcnt(0x0F73);   // vmcnt <= 3: the row fetches are done, the 3 stream loads may fly
+            for (int t = 0; t < 16; ++t) operand(t, av[t], bv[t]);
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (t < nsteps) acc = Acc<float>::mfma(av[t], bv[t], acc);
         } else {
-            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt = 0
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float xs[16];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const float4 t4 = *(const float4*)&s_x[w][kq * 16 + 4 * v];
-            xs[4 * v] = t4.x; xs[4 * v + 1] = t4.y; xs[4 * v + 2] = t4.z; xs[4 * v + 3] = t4.w;
-        }
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            if (t < nsteps) {
+            for (int t = 0; t < nsteps; ++t) {
                 if (((starts >> (4 * t)) & 1ull) && (p + 4 * t != q0)) {
                     flush(s);
                     ++s;
                     acc = f4_t{0, 0, 0, 0};
                 }
-                const int e = (4 * t + kq) * 16 + m;
                 float av, bv;
-                if constexpr (sizeof(ST) == 4) { av = sA[w][e]; bv = sB[w][e]; }
-                else { av = bf16_to_f32(sA[w][e]); bv = bf16_to_f32(sB[w][e]); }
-                acc = Acc<float>::mfma(av * xs[t], bv, acc);
+                operand(t, av, bv);
+                acc = Acc<float>::mfma(av, bv, acc);
             }
         }
+        // 4. batch b+1's rows into the tile
+        TK_PUT()
+        starts = starts_next;
+        xb ^= 1;
     }
     flush(s);
+#undef TK_G1
+#undef TK_P1
+#undef TK_GATHER
+#undef TK_PUT
 }
 
 template <typename AT, typename ST, int KPL>
@@ -339,7 +394,7 @@ __global__ __launch_bounds__(256) void k_ttmc_generic(TtmcArgs a) {
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int ch = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int ch = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     if (ch >= a.nchunks) return;
     const int q0 = a.chunk_ptr[ch], q1 = a.chunk_ptr[ch + 1];
     const int slot = a.chunk_slot[ch];
