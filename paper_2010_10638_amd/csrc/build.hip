@@ -200,46 +200,48 @@ int launch_gather(const int32_t* perm, int64_t D, const int32_t* rowsrc, const G
     return TK_OK;
 }
 
-// Greedy chunking of the padded stream: whole rows are packed into chunks of at most L entries; a
-// row longer than L is cut into pieces of L (L a multiple of 64), and every piece after the first
-// is a carrier whose partial row sum goes to a carry slot and is added by the fix-up pass.
-void make_chunks(const std::vector<int32_t>& ptr, int64_t L, std::vector<int32_t>& cptr,
+// Balanced chunking of the padded stream: C pieces of (nearly) equal length, each a multiple of
+// 4 entries, cut anywhere - a piece may start inside a row.  The piece where a row starts owns it
+// (writes Y_(n) directly); every later piece holding part of that row is a carrier whose partial
+// row sum goes to a carry slot, added to the row by the fix-up pass in slot order.  Equal pieces
+// give every wave the same work whatever the row-length distribution (skewed fibers included).
+void make_chunks(const std::vector<int32_t>& ptr, int64_t C, std::vector<int32_t>& cptr,
                  std::vector<int32_t>& crow, std::vector<int32_t>& cslot,
                  std::vector<int32_t>& split, int64_t& ncarry, int32_t& maxrow) {
     const int64_t S = (int64_t)ptr.size() - 1;
+    const int64_t D = ptr[S];
     ncarry = 0;
     maxrow = 0;
-    int64_t s = 0;
-    while (s < S) {
-        int64_t len = (int64_t)ptr[s + 1] - ptr[s];
-        maxrow = std::max<int32_t>(maxrow, (int32_t)len);
-        if (len > L) {
-            int64_t pieces = (len + L - 1) / L;
-            int64_t first = ncarry;
-            for (int64_t k = 0; k < pieces; ++k) {
-                cptr.push_back((int32_t)(ptr[s] + k * L));
-                crow.push_back((int32_t)s);
-                cslot.push_back(k == 0 ? -1 : (int32_t)(ncarry++));
-            }
-            split.push_back((int32_t)s);
-            split.push_back((int32_t)first);
-            split.push_back((int32_t)(ncarry - 1));
-            ++s;
-        } else {
-            cptr.push_back(ptr[s]);
-            crow.push_back((int32_t)s);
+    for (int64_t r = 0; r < S; ++r) maxrow = std::max<int32_t>(maxrow, ptr[r + 1] - ptr[r]);
+    if (D == 0) {
+        cptr.push_back(0);
+        return;
+    }
+    const int64_t quads = D / 4;
+    C = std::max<int64_t>(1, std::min<int64_t>(C, quads));
+    int64_t r = 0;            // row holding the current piece start
+    int64_t open_row = -1;    // row with carry slots being collected
+    for (int64_t k = 0; k < C; ++k) {
+        const int64_t q = quads * k / C * 4;
+        if (!cptr.empty() && q == cptr.back()) continue;
+        while (ptr[r + 1] <= q) ++r;
+        cptr.push_back((int32_t)q);
+        crow.push_back((int32_t)r);
+        if (ptr[r] == q) {
             cslot.push_back(-1);
-            int64_t total = 0;
-            while (s < S) {
-                int64_t l2 = (int64_t)ptr[s + 1] - ptr[s];
-                if (l2 > L || total + l2 > L) break;
-                maxrow = std::max<int32_t>(maxrow, (int32_t)l2);
-                total += l2;
-                ++s;
+        } else {
+            if (open_row != r) {
+                split.push_back((int32_t)r);
+                split.push_back((int32_t)ncarry);
+                split.push_back((int32_t)ncarry);
+                open_row = r;
+            } else {
+                split.back() = (int32_t)ncarry;
             }
+            cslot.push_back((int32_t)(ncarry++));
         }
     }
-    cptr.push_back(ptr[S]);
+    cptr.push_back((int32_t)D);
 }
 
 template <typename T>
@@ -359,7 +361,11 @@ int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t
 
     // 3. per mode: sort by the mode key, gather the SoA layout, row pointers, chunk table
     const int32_t* dc = (const int32_t*)dco.p;
-    const int64_t L = std::min<int64_t>(2048, std::max<int64_t>(64, (D / 8192 + 63) / 64 * 64));
+    // chunk count: kChunkWavesPerCU resident waves per compute unit, pieces of at least 256 entries
+    int ncu = 0;
+    TK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const int64_t nchunk_target =
+        std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(ncu, 1) * kChunkWavesPerCU, D / 256));
     for (int m = 0; m < N; ++m) {
         ModeLayout& ml = ctx->mode[m];
         int no = 0;
@@ -468,7 +474,7 @@ int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t
             TK_LAUNCH_CHECK("k_pad_scatter");
         }
         std::vector<int32_t> cptr, crow, cslot, split;
-        make_chunks(hpptr, L, cptr, crow, cslot, split, ml.ncarry, ml.max_row_nnz);
+        make_chunks(hpptr, nchunk_target, cptr, crow, cslot, split, ml.ncarry, ml.max_row_nnz);
         ml.nchunks = (int64_t)crow.size();
         ml.nsplit = (int64_t)split.size() / 3;
         if ((st = upload(&ml.chunk_ptr, cptr, s)) || (st = upload(&ml.chunk_row, crow, s)) ||

@@ -13,6 +13,11 @@ namespace tk {
 
 constexpr int kMaxOrder = TK_MAX_ORDER;
 constexpr int kMaxK = TK_MAX_KCOLS;
+#ifndef TK_CHUNK_WAVES_PER_CU
+#define TK_CHUNK_WAVES_PER_CU 16
+#endif
+// TTMc work split: pieces of the nonzero stream per compute unit (one wave each)
+constexpr int kChunkWavesPerCU = TK_CHUNK_WAVES_PER_CU;
 constexpr int kPadR = 16;          // factor copies are padded to a multiple of 16 columns
 constexpr int kGramMaxR = 32;      // Gram/Cholesky QRP route handles R_n up to this
 
