@@ -12,18 +12,21 @@ typedef double atb_d4_t __attribute__((ext_vector_type(4)));
 // chunk's loads are issued before the current chunk's MFMAs) into LDS, converted to FP64; wave w
 // computes the 16 output rows a0+16w.. across the 64 output columns (4 tiles of
 // v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
-// D[l/16 + 4v][l%16] in result v).  Columns past na / nb read as zero.
+// D[l/16 + 4v][l%16] in result v).  Columns past na / nb read as zero.  Requires r0 < r1,
+// a0 < na and b0 < nbc.
+// Raw loads of one 32-row chunk: every load is issued unconditionally from a clamped (valid)
+// address, so all 16 are in flight together; masking and the conversion to FP64 happen when the
+// chunk is written to LDS, after the MFMAs of the previous chunk.
 template <typename AT, typename BT>
 __device__ inline void atb_stage(const AT* __restrict__ A, int lda, int na, const BT* __restrict__ B, int ldb,
-                                 int nbc, int64_t row0, int64_t r1, int a0, int b0, double* va, double* vb) {
+                                 int nbc, int64_t row0, int64_t r1, int a0, int b0, AT* xa, BT* xb) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int e = threadIdx.x + 256 * k;
         const int rr = e >> 6, cc = e & 63;
-        const int64_t row = row0 + rr;
-        const bool rv = row < r1;
-        va[k] = (rv && a0 + cc < na) ? (double)A[row * lda + a0 + cc] : 0.0;
-        vb[k] = (rv && b0 + cc < nbc) ? (double)B[row * ldb + b0 + cc] : 0.0;
+        const int64_t row = min(row0 + rr, r1 - 1);
+        xa[k] = A[row * lda + (a0 + cc < na ? a0 + cc : a0)];
+        xb[k] = B[row * ldb + (b0 + cc < nbc ? b0 + cc : b0)];
     }
 }
 
@@ -33,18 +36,21 @@ __device__ void atb_block(const AT* __restrict__ A, int lda, int na, const BT* _
                           double (*Bs)[32][65], atb_d4_t* acc) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int kq = lane >> 4, c16 = lane & 15;
-    double va[8], vb[8];
-    atb_stage(A, lda, na, B, ldb, nbc, r0, r1, a0, b0, va, vb);
+    AT xa[8];
+    BT xb[8];
+    atb_stage(A, lda, na, B, ldb, nbc, r0, r1, a0, b0, xa, xb);
     int buf = 0;
     for (int64_t row0 = r0; row0 < r1; row0 += 32) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int e = threadIdx.x + 256 * k;
-            As[buf][e >> 6][e & 63] = va[k];
-            Bs[buf][e >> 6][e & 63] = vb[k];
+            const int rr = e >> 6, cc = e & 63;
+            const bool rv = row0 + rr < r1;
+            As[buf][rr][cc] = (rv && a0 + cc < na) ? (double)xa[k] : 0.0;
+            Bs[buf][rr][cc] = (rv && b0 + cc < nbc) ? (double)xb[k] : 0.0;
         }
         __syncthreads();
-        if (row0 + 32 < r1) atb_stage(A, lda, na, B, ldb, nbc, row0 + 32, r1, a0, b0, va, vb);
+        if (row0 + 32 < r1) atb_stage(A, lda, na, B, ldb, nbc, row0 + 32, r1, a0, b0, xa, xb);
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
             const int rr = 4 * st + kq;

@@ -61,9 +61,7 @@ __global__ void k_core_reduce(const double* __restrict__ part, int nsplit, int K
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)K * R) return;
     const int r = (int)(e / K), c = (int)(e % K);
-    double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += part[((int64_t)k * R + r) * K + c];
-    G[(int64_t)c * R + r] = s;
+    G[(int64_t)c * R + r] = sum_strided(part + (int64_t)r * K + c, nsplit, (int64_t)R * K);
 }
 
 // ||G||^2 (fixed-order tree) and fit = 1 - sqrt(max(||X||^2 - ||G||^2, 0)) / ||X||.

@@ -135,6 +135,30 @@ int hip_error(hipError_t e, const char* what);
         if (e_ != hipSuccess) return ::tk::hip_error(e_, what);       \
     } while (0)
 
+// value of v in lane src (src wave-uniform), through two v_readlane (no LDS round trip)
+__device__ inline double wave_bcast(double v, int src) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// sum_{k < cnt} p[k * stride], added in k order; the loads are issued eight at a time so they
+// overlap (the order of the additions, hence the result, is that of the plain loop)
+__device__ inline double sum_strided(const double* __restrict__ p, int cnt, int64_t stride) {
+    double s = 0.0;
+    int k = 0;
+    for (; k + 8 <= cnt; k += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(k + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; k < cnt; ++k) s += p[(int64_t)k * stride];
+    return s;
+}
+
 // Layout builder (build.hip)
 int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t nnz_in,
                  hipStream_t s);

@@ -76,133 +76,151 @@ __global__ void k_gram_reduce(const double* __restrict__ part, int nsplit, int n
     if (e >= (int64_t)n * n) return;
     const int i = (int)(e / n), j = (int)(e % n);
     if ((i >> 6) > (j >> 6)) return;
-    double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n * n + e];
+    const double s = sum_strided(part + e, nsplit, (int64_t)n * n);
     C[e] = s;
     if ((i >> 6) != (j >> 6)) C[(int64_t)j * n + i] = s;
 }
 
-// Pivoted Cholesky of C (n <= 1024), R steps, one workgroup of 1024 threads; thread t owns
-// position t of the (physically swapped) column order.  L is stored transposed, entry (c, i) at
-// i * n + c, in LDS when it fits (lds_L != 0), else in the global workspace.  C is symmetric, so
-// column cs is read as row cs.
+// Pivoted Cholesky of C (n <= 1024), R steps, one workgroup of ceil(n/64) waves; thread t owns
+// position t of the (physically swapped) column order and keeps that position's column id and
+// Schur-complement diagonal in registers.  Per step: a block argmax (first maximum) of the
+// diagonals at positions >= j, one barrier, then the swap of positions j and the winner done by
+// the two threads involved, and the new row of L^T (entry (i, c) at i * n + c, indexed by column
+// id) from one row of C (C is symmetric, so column cs is read as row cs).  Per-step LDS slots
+// are double-buffered, so one barrier per step orders everything.  L lives in LDS when kLdsL.
+// R11^{-1} is formed by column-oriented back substitution, one wave per column.
+template <bool kLdsL>
 __global__ __launch_bounds__(1024) void k_pivchol(const double* __restrict__ C, int n, int R,
-                                                  double* __restrict__ Lg, int lds_L,
+                                                  double* __restrict__ Lg,
                                                   double* __restrict__ R11, double* __restrict__ Rinv,
                                                   int32_t* __restrict__ pivw, int32_t* __restrict__ flag) {
     extern __shared__ double Ls[];
-    __shared__ double d[1024];
-    __shared__ int perm[1024];
-    __shared__ double lrow[32];
-    __shared__ double rv[16];
-    __shared__ int rp[16];
-    __shared__ double dmax0;
-    double* L = lds_L ? Ls : Lg;
-    const int tid = threadIdx.x;
-    if (tid < n) { d[tid] = C[(int64_t)tid * n + tid]; perm[tid] = tid; }
-    if (tid == 0) *flag = 0;
-    __syncthreads();
+    __shared__ double s_wv[2][16];
+    __shared__ int s_wp[2][16];
+    __shared__ int s_wc[2][16];
+    __shared__ int s_jcol[2];
+    __shared__ double s_jd[2];
+    __shared__ double s_mx[16];
+    __shared__ int s_piv[32];
+    __shared__ double sR[32][33];
+    double* L;
+    if constexpr (kLdsL) L = Ls;
+    else L = Lg;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nw = (int)(blockDim.x >> 6);
+    int mycol = tid;
+    double myd = (tid < n) ? C[(int64_t)tid * n + tid] : -1.0;
+    double dmax0;
     {
-        double v = (tid < n) ? d[tid] : -1.0;
+        double v = myd;
         for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-        if ((tid & 63) == 0) rv[tid >> 6] = v;
+        if (lane == 0) s_mx[wid] = v;
         __syncthreads();
-        if (tid == 0) {
-            double mx = rv[0];
-            for (int k = 1; k < 16; ++k) mx = fmax(mx, rv[k]);
-            dmax0 = mx;
-        }
-        __syncthreads();
+        dmax0 = s_mx[0];
+        for (int k = 1; k < nw; ++k) dmax0 = fmax(dmax0, s_mx[k]);
     }
     bool bad = false;
     for (int j = 0; j < R; ++j) {
-        double v = -1.0;
-        int p = n;
-        if (tid >= j && tid < n) { v = d[perm[tid]]; p = tid; }
-        for (int o = 32; o > 0; o >>= 1) {
-            double v2 = __shfl_xor(v, o);
-            int p2 = __shfl_xor(p, o);
-            if (v2 > v || (v2 == v && p2 < p)) { v = v2; p = p2; }
-        }
-        if ((tid & 63) == 0) { rv[tid >> 6] = v; rp[tid >> 6] = p; }
-        __syncthreads();
-        if (tid == 0) {
-            double bv = rv[0];
-            int bp = rp[0];
-            for (int k = 1; k < 16; ++k)
-                if (rv[k] > bv || (rv[k] == bv && rp[k] < bp)) { bv = rv[k]; bp = rp[k]; }
-            int t = perm[j]; perm[j] = perm[bp]; perm[bp] = t;
+        const int b = j & 1;
+        if (tid == j) { s_jcol[b] = mycol; s_jd[b] = myd; }
+        // wave argmax: the maximum value, then the lowest lane holding it (positions grow with lanes)
+        const bool cand = tid >= j && tid < n;
+        const double v = cand ? myd : -INFINITY;
+        double mx = v;
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+        const uint64_t hold = __ballot(cand && v == mx);
+        const int hl = hold ? (int)__builtin_ctzll(hold) : 0;
+        const int hcol = __builtin_amdgcn_readlane(mycol, hl);
+        if (lane == 0) {
+            s_wv[b][wid] = hold ? mx : -INFINITY;
+            s_wp[b][wid] = hold ? wid * 64 + hl : n;
+            s_wc[b][wid] = hcol;
         }
         __syncthreads();
-        const int cs = perm[j];
-        const double djj = d[cs];
+        double bv = s_wv[b][0];
+        int bp = s_wp[b][0], bc = s_wc[b][0];
+        for (int k = 1; k < nw; ++k) {
+            const double v2 = s_wv[b][k];
+            const int p2 = s_wp[b][k];
+            if (v2 > bv || (v2 == bv && p2 < bp)) { bv = v2; bp = p2; bc = s_wc[b][k]; }
+        }
+        if (bp >= n) { bp = j; bc = s_jcol[b]; bv = s_jd[b]; }   // no comparable candidate (NaN)
+        const int cs = bc;
+        const double djj = bv;
+        if (tid == bp && bp != j) { mycol = s_jcol[b]; myd = s_jd[b]; }
+        if (tid == j) { mycol = cs; myd = djj; }
         if (!(djj > 1e-12 * dmax0)) bad = true;
         const double ljj = bad ? 1.0 : sqrt(djj);
-        if (tid < j) lrow[tid] = L[(int64_t)tid * n + cs];
-        __syncthreads();
-        if (tid == 0) L[(int64_t)j * n + cs] = ljj;
+        if (tid == j) L[(int64_t)j * n + cs] = ljj;
         if (tid > j && tid < n) {
-            const int c = perm[tid];
+            const int c = mycol;
             double acc = C[(int64_t)cs * n + c];
-            for (int i = 0; i < j; ++i) acc -= L[(int64_t)i * n + c] * lrow[i];
+#pragma unroll 8
+            for (int i = 0; i < j; ++i) acc -= L[(int64_t)i * n + c] * L[(int64_t)i * n + cs];
             const double l = acc / ljj;
             L[(int64_t)j * n + c] = l;
-            d[c] -= l * l;
+            myd -= l * l;
         }
-        __syncthreads();
     }
-    if (tid < R) pivw[tid] = perm[tid];
-    __shared__ double sR11[32 * 32];
+    if (tid < R) s_piv[tid] = mycol;
+    __syncthreads();
+    if (tid < R) pivw[tid] = mycol;
     for (int e = tid; e < R * R; e += blockDim.x) {
-        const int i = e / R, j = e % R;
-        const double r = (i <= j) ? L[(int64_t)i * n + perm[j]] : 0.0;
+        const int i = e / R, jj = e % R;
+        const double r = (i <= jj) ? L[(int64_t)i * n + s_piv[jj]] : 0.0;
         R11[e] = r;
-        sR11[e] = r;
+        sR[i][jj] = r;
     }
     __syncthreads();
-    __shared__ double x[32][33];
-    if (tid < R) {  // column tid of R11^{-1} by back substitution
-        const int c = tid;
-        for (int i = R - 1; i >= 0; --i) {
-            double acc = (i == c) ? 1.0 : 0.0;
-            for (int k = i + 1; k <= c; ++k) acc -= sR11[i * R + k] * x[c][k];
-            x[c][i] = (i <= c) ? acc / sR11[i * R + i] : 0.0;
-            Rinv[i * R + c] = x[c][i];
+    // column c of R11^{-1}: lane i holds b_i; step k finalises x_k = b_k / r_kk and removes it
+    for (int c = wid; c < R; c += nw) {
+        double bi = (lane == c) ? 1.0 : 0.0;
+        double xi = 0.0;
+        for (int k = c; k >= 0; --k) {
+            const double xk = wave_bcast(bi / sR[k][k], k);
+            if (lane == k) xi = xk;
+            if (lane < k) bi -= sR[lane][k] * xk;
         }
+        if (lane < R) Rinv[lane * R + c] = (lane <= c) ? xi : 0.0;
     }
-    if (bad && tid == 0) *flag = 1;
+    if (tid == 0) *flag = bad ? 1 : 0;
 }
 
-// Q1 = Y[:, piv] R11^{-1} (one row per thread, as b times the precomputed upper-triangular
-// inverse, so the R outputs of a row are independent sums) and the partial Gram Q1^T Q1 of the
-// workgroup's 256 rows, one entry per thread.
+// Q1 = Y[:, piv] R11^{-1} and the partial Gram Q1^T Q1 of the workgroup's 64 rows.  Four
+// threads share a row (thread (r, g) forms q[r][c] for c = g, g + 4, ..., each as b times the
+// precomputed upper-triangular inverse, so the R outputs of a row are independent sums), then one
+// Gram entry per thread.  No flag check: after a breakdown the values are unused.
 template <typename YT>
 __global__ __launch_bounds__(256) void k_q1_gram(const YT* __restrict__ Y, int64_t m, int n, int R,
                                                  const int32_t* __restrict__ pivw,
                                                  const double* __restrict__ Rinv,
-                                                 const int32_t* __restrict__ flag,
                                                  double* __restrict__ part2) {
-    if (*flag) return;
     __shared__ double sRi[32 * 32];
     __shared__ int sp[32];
-    __shared__ double q[256][33];
+    __shared__ double q[64][33];
     const int tid = threadIdx.x;
     for (int e = tid; e < R * R; e += 256) sRi[e] = Rinv[e];
     if (tid < R) sp[tid] = pivw[tid];
     __syncthreads();
-    const int64_t row = (int64_t)blockIdx.x * 256 + tid;
+    const int r = tid >> 2, g = tid & 3;
+    const int64_t row = (int64_t)blockIdx.x * 64 + r;
+    // unconditional loads from clamped addresses (all in flight together), masked afterwards
+    const int64_t rowc = row < m ? row : m - 1;
     double b[32];
 #pragma unroll
-    for (int j = 0; j < 32; ++j) b[j] = (j < R && row < m) ? yld(Y, row * n + sp[j]) : 0.0;
-    for (int c = 0; c < R; ++c) {
+    for (int j = 0; j < 32; ++j) b[j] = yld(Y, rowc * n + sp[j < R ? j : 0]);
+#pragma unroll
+    for (int j = 0; j < 32; ++j) b[j] = (j < R && row < m) ? b[j] : 0.0;
+    for (int c = g; c < R; c += 4) {
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < 32; ++i)
             if (i <= c && i < R) acc += b[i] * sRi[i * R + c];
-        q[tid][c] = acc;
+        q[r][c] = acc;
     }
     __syncthreads();
-    const int nr = (int)min<int64_t>(256, m - (int64_t)blockIdx.x * 256);
+    const int nr = (int)min<int64_t>(64, m - (int64_t)blockIdx.x * 64);
     for (int pr = tid; pr < R * R; pr += 256) {
         const int a = pr / R, bb = pr % R;
         double acc = 0.0;
@@ -228,115 +246,103 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
     if (threadIdx.x == 0) out[e] = red[0];
 }
 
-// Sum the Gram partials, Cholesky them, fold in R11^{-1}, fix the Householder signs:
-// M = R11^{-1} R2^{-1} S, so that U = Y[:, piv] M.  One workgroup; the R x R algebra is spread
-// over the threads of one wave (one column or row of the triangular solves per thread).
-template <typename YT>
-__global__ __launch_bounds__(256) void k_qrp_finish(const YT* __restrict__ Y, int n, int R,
-                                                    const int32_t* __restrict__ pivw,
-                                                    const double* __restrict__ Rinv,
-                                                    const double* __restrict__ G2in,
-                                                    int32_t* __restrict__ flag, double* __restrict__ Mout,
-                                                    int32_t* __restrict__ piv_out) {
+// Finishing algebra of route 0 in one wave, register-resident (RMAX >= R, RMAX in {8, 16, 32}):
+//   Cholesky G2 = R2^T R2 (Gram of Q1; lane c holds column c, right-looking, broadcasts by
+//   v_readlane);  M' = R11^{-1} R2^{-1} (lane i solves row i of M' R2 = R11^{-1});
+//   T = Y[0:R, piv] M';  sign rule: LU of (T S - I) without pivoting with s_j chosen so that each
+//   pivot is <= -1 (lane i holds row i of T);  M = M' S, so that U = Y[:, piv] M.
+// A Cholesky breakdown sets the device flag (the gated Householder kernel then runs).
+template <typename YT, int RMAX, bool kExact>
+__global__ __launch_bounds__(64) void k_qrp_finish(const YT* __restrict__ Y, int n, int R_arg,
+                                                   const int32_t* __restrict__ pivw,
+                                                   const double* __restrict__ Rinv,
+                                                   const double* __restrict__ G2in,
+                                                   int32_t* __restrict__ flag, double* __restrict__ Mout,
+                                                   int32_t* __restrict__ piv_out) {
     if (*flag) return;
-    __shared__ double G2[32 * 32];   // Gram of Q1, then M' = R11^{-1} R2^{-1}
-    __shared__ double A[32 * 32];    // R2 (upper)
-    __shared__ double Bi[32 * 32];   // R11^{-1} (upper), computed by k_pivchol
-    __shared__ double T[32 * 32];    // top R x R block of Y[:, piv] M', then its LU
-    __shared__ double Bt[32 * 32];   // Y[0:R, piv]
-    __shared__ double sgn[32];
-    __shared__ int bad;
-    const int tid = threadIdx.x;
-    const int nt = blockDim.x;
-    for (int e = tid; e < R * R; e += nt) {
-        G2[e] = G2in[e];
-        A[e] = 0.0;
-        Bi[e] = Rinv[e];
-        Bt[e] = yld(Y, (int64_t)(e / R) * n + pivw[e % R]);
+    const int R = kExact ? RMAX : R_arg;     // kExact: R == RMAX, the guards below fold away
+    __shared__ double sR2[RMAX][RMAX + 1];   // R2 (upper)
+    __shared__ double sM[RMAX][RMAX + 1];    // M'
+    const int lane = threadIdx.x;
+    const bool live = lane < R;
+    const int lr = live ? lane : 0;
+    double w[RMAX], t[RMAX];
+    // lane c: column c of G2; lane i: row i of R11^{-1} (t) - loads in flight together
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+        const int kk = k < R ? k : 0;
+        w[k] = G2in[kk * R + lr];
+        t[k] = Rinv[lr * R + kk];
     }
-    if (tid == 0) bad = 0;
-    __syncthreads();
-    // Cholesky G2 = R2^T R2, row j of R2 per step
-    for (int j = 0; j < R; ++j) {
-        if (tid == 0) {
-            double d = G2[j * R + j];
-            for (int k = 0; k < j; ++k) d -= A[k * R + j] * A[k * R + j];
-            if (!(d > 0.0)) bad = 1;
-            A[j * R + j] = (d > 0.0) ? sqrt(d) : 1.0;
+    bool bad = false;
+    // Cholesky, right-looking: after step j, w[j] of lane c is R2[j][c]
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+        if (j < R) {
+            const double d = wave_bcast(w[j], j);
+            if (!(d > 0.0)) bad = true;
+            const double rjj = (d > 0.0) ? sqrt(d) : 1.0;
+            const double r = (lane == j) ? rjj : ((lane > j) ? w[j] / rjj : 0.0);
+            w[j] = r;
+#pragma unroll
+            for (int k = j + 1; k < RMAX; ++k)
+                if (k < R) w[k] -= wave_bcast(r, k) * r;
         }
-        __syncthreads();
-        const int c = j + 1 + tid;
+    }
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k)
+        if (live && k < R) sR2[k][lane] = w[k];
+    __syncthreads();
+    // row i of M' = row i of R11^{-1} times R2^{-1}: forward substitution over columns
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
         if (c < R) {
-            double acc = G2[j * R + c];
-            for (int k = 0; k < j; ++k) acc -= A[k * R + j] * A[k * R + c];
-            A[j * R + c] = acc / A[j * R + j];
-        }
-        __syncthreads();
-    }
-    // M' = Bi R2^{-1}: row i by forward substitution over columns (thread i)
-    if (tid < R) {
-        const int i = tid;
-        for (int c = 0; c < R; ++c) {
-            double acc = Bi[i * R + c];
-            for (int k = 0; k < c; ++k) acc -= G2[i * R + k] * A[k * R + c];
-            G2[i * R + c] = acc / A[c * R + c];
+            double acc = t[c];
+#pragma unroll
+            for (int k = 0; k < c; ++k) acc -= t[k] * sR2[k][c];
+            t[c] = acc / sR2[c][c];
         }
     }
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c)
+        if (live && c < R) sM[lane][c] = t[c];
+    // row i of Y[0:R, piv] (w), then row i of T = Y[0:R, piv] M' (t)
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) w[k] = yld(Y, (int64_t)lr * n + pivw[k < R ? k : 0]);
     __syncthreads();
-    // T = Bt M'
-    for (int e = tid; e < R * R; e += nt) {
-        const int i = e / R, c = e % R;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
         double acc = 0.0;
-        for (int k = 0; k < R; ++k) acc += Bt[i * R + k] * G2[k * R + c];
-        T[e] = acc;
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k)
+            if (k < R) acc += w[k] * sM[k][c];
+        t[c] = acc;
     }
-    __syncthreads();
-    // sign rule: LU of (T S - I) without pivoting, s_j chosen so that the pivot is <= -1
-    for (int j = 0; j < R; ++j) {
-        if (tid == 0) sgn[j] = (T[j * R + j] >= 0.0) ? -1.0 : 1.0;
-        __syncthreads();
-        if (tid < R) {
-            T[tid * R + j] *= sgn[j];
-            if (tid == j) T[j * R + j] -= 1.0;
+    // sign rule on the LU of T S - I (lane i holds row i)
+    double sg[RMAX];
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+        sg[j] = 1.0;
+        if (j < R) {
+            sg[j] = (wave_bcast(t[j], j) >= 0.0) ? -1.0 : 1.0;
+            t[j] *= sg[j];
+            if (lane == j) t[j] -= 1.0;
+            const double pv = wave_bcast(t[j], j);
+            const double f = t[j] / pv;
+#pragma unroll
+            for (int c = j + 1; c < RMAX; ++c) {
+                const double tjc = wave_bcast(t[c], j);
+                if (c < R && lane > j) t[c] -= f * tjc;
+            }
         }
-        __syncthreads();
-        const double pv = T[j * R + j];
-        for (int e = tid; e < (R - j - 1) * (R - j - 1); e += nt) {
-            const int i = j + 1 + e / (R - j - 1), c = j + 1 + e % (R - j - 1);
-            T[i * R + c] -= (T[i * R + j] / pv) * T[j * R + c];
-        }
-        __syncthreads();
     }
-    for (int e = tid; e < R * R; e += nt) Mout[e] = G2[e] * sgn[e % R];
-    if (piv_out && tid < R) piv_out[tid] = pivw[tid];
-    if (tid == 0 && bad) *flag = 1;
-}
-
-// U = Y[:, piv] M and its low-precision copy; 16 consecutive threads share a row, one output
-// column each (columns R..ldlp-1 of the copy are zeroed).
-template <typename YT, typename LT>
-__global__ __launch_bounds__(256) void k_form_u(const YT* __restrict__ Y, int64_t m, int n, int R,
-                                                const int32_t* __restrict__ pivw,
-                                                const double* __restrict__ M,
-                                                const int32_t* __restrict__ flag,
-                                                double* __restrict__ U, LT* __restrict__ Ulp, int ldlp) {
-    if (*flag) return;
-    __shared__ double sM[32 * 32];
-    __shared__ int sp[32];
-    for (int e = threadIdx.x; e < R * R; e += 256) sM[e] = M[e];
-    if (threadIdx.x < R) sp[threadIdx.x] = pivw[threadIdx.x];
-    __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t row = g / ldlp;
-    const int c = (int)(g % ldlp);
-    if (row >= m) return;
-    double u = 0.0;
-    if (c < R)
-        for (int j = 0; j < R; ++j) u += yld(Y, row * n + sp[j]) * sM[j * R + c];
-    if (c < R) U[row * R + c] = u;
-    if constexpr (sizeof(LT) == 8) Ulp[row * ldlp + c] = u;
-    else if constexpr (sizeof(LT) == 4) Ulp[row * ldlp + c] = (float)u;
-    else Ulp[row * ldlp + c] = f32_to_bf16((float)u);
+    if (live) {
+#pragma unroll
+        for (int c = 0; c < RMAX; ++c)
+            if (c < R) Mout[lane * R + c] = sM[lane][c] * sg[c];
+        if (piv_out) piv_out[lane] = pivw[lane];
+    }
+    if (lane == 0 && bad) *flag = 1;
 }
 
 // ---- Routes 1 and 2 ------------------------------------------------------------------------
@@ -362,16 +368,14 @@ __device__ inline double block_sum(double v, double* red) {
     return s;
 }
 
-// Eager Householder QRP on A (m x n, FP64, in place), R steps, one workgroup of 1024 threads,
-// then Q[:, :R] = H_0 ... H_{R-1} [I; 0] into U (m x R) and the low-precision copy.
+// Eager Householder QRP on A (m x n, FP64, in place), R steps, by one workgroup (any size up to
+// 1024 threads), then Q[:, :R] = H_0 ... H_{R-1} [I; 0] into U (m x R) and the low-precision copy.
 template <typename YT, typename LT>
-__global__ __launch_bounds__(1024) void k_house_qrp(const YT* __restrict__ src, double* __restrict__ A, int64_t m, int n, int R,
-                                                    double* __restrict__ V, double* __restrict__ w,
-                                                    double* __restrict__ beta_s, int32_t* __restrict__ perm,
-                                                    const int32_t* __restrict__ gate, int gate_val,
-                                                    double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
-                                                    int32_t* __restrict__ piv_out) {
-    if (gate && *gate != gate_val) return;
+__device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ A, int64_t m, int n, int R,
+                               double* __restrict__ V, double* __restrict__ w,
+                               double* __restrict__ beta_s, int32_t* __restrict__ perm,
+                               double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
+                               int32_t* __restrict__ piv_out) {
     __shared__ double red[16];
     __shared__ double rv[16];
     __shared__ int rp[16];
@@ -480,6 +484,50 @@ __global__ __launch_bounds__(1024) void k_house_qrp(const YT* __restrict__ src, 
     if (piv_out && tid < R) piv_out[tid] = perm[tid];
 }
 
+template <typename YT, typename LT>
+__global__ __launch_bounds__(1024) void k_house_qrp(const YT* __restrict__ src, double* __restrict__ A, int64_t m, int n, int R,
+                                                    double* __restrict__ V, double* __restrict__ w,
+                                                    double* __restrict__ beta_s, int32_t* __restrict__ perm,
+                                                    double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
+                                                    int32_t* __restrict__ piv_out) {
+    house_qrp_body<YT, LT>(src, A, m, n, R, V, w, beta_s, perm, U, Ulp, ldlp, piv_out);
+}
+
+// U = Y[:, piv] M and its low-precision copy; 16 consecutive threads share a row, one output
+// column each (columns R..ldlp-1 of the copy are zeroed).
+// After a breakdown (device flag set) workgroup 0 runs the Householder QRP on Y instead and the
+// others exit.
+template <typename YT, typename LT>
+__global__ __launch_bounds__(256) void k_form_u(const YT* __restrict__ Y, int64_t m, int n, int R,
+                                                const int32_t* __restrict__ pivw,
+                                                const double* __restrict__ M,
+                                                const int32_t* __restrict__ flag,
+                                                double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
+                                                double* __restrict__ A, double* __restrict__ V,
+                                                double* __restrict__ wv, double* __restrict__ beta_s,
+                                                int32_t* __restrict__ perm, int32_t* __restrict__ piv_out) {
+    if (*flag) {
+        if (blockIdx.x == 0) house_qrp_body<YT, LT>(Y, A, m, n, R, V, wv, beta_s, perm, U, Ulp, ldlp, piv_out);
+        return;
+    }
+    __shared__ double sM[32 * 32];
+    __shared__ int sp[32];
+    for (int e = threadIdx.x; e < R * R; e += 256) sM[e] = M[e];
+    if (threadIdx.x < R) sp[threadIdx.x] = pivw[threadIdx.x];
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t row = g / ldlp;
+    const int c = (int)(g % ldlp);
+    if (row >= m) return;
+    double u = 0.0;
+    if (c < R)
+        for (int j = 0; j < R; ++j) u += yld(Y, row * n + sp[j]) * sM[j * R + c];
+    if (c < R) U[row * R + c] = u;
+    if constexpr (sizeof(LT) == 8) Ulp[row * ldlp + c] = u;
+    else if constexpr (sizeof(LT) == 4) Ulp[row * ldlp + c] = (float)u;
+    else Ulp[row * ldlp + c] = f32_to_bf16((float)u);
+}
+
 struct QrpPlan {
     int route;
     int64_t m;       // rows of the QRP input
@@ -521,8 +569,8 @@ QrpPlan plan(const tk_ctx* ctx, int mode) {
         p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(p.m + 127) / 128, want, cap}));
         p.slab = ((p.m + p.nsplit - 1) / p.nsplit + 31) / 32 * 32;
         p.nsplit = (int)((p.m + p.slab - 1) / p.slab);
-        p.rows2 = 256;
-        p.nblk2 = (int)((p.m + 255) / 256);
+        p.rows2 = 64;
+        p.nblk2 = (int)((p.m + 63) / 64);
         p.o_part = off; off += (int64_t)p.nsplit * nn;
         p.o_C = off; off += nn;
         p.o_L = off; off += (int64_t)p.n * R;
@@ -561,30 +609,37 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
         k_gram_reduce<<<cdiv((int64_t)p.n * p.n, 256), 256, 0, s>>>(W + p.o_part, p.nsplit, p.n, W + p.o_C);
         TK_LAUNCH_CHECK("k_gram_reduce");
         const size_t lsz = (size_t)p.n * p.R * sizeof(double);
-        const int lds_L = lsz <= 64 * 1024 ? 1 : 0;
-        k_pivchol<<<1, 1024, lds_L ? lsz : 0, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, lds_L, W + p.o_R11, W + p.o_Rinv,
-                                                     pivw, flag);
+        const unsigned nthr = (unsigned)std::max(64, (p.n + 63) / 64 * 64);
+        if (lsz <= 64 * 1024)
+            k_pivchol<true><<<1, nthr, lsz, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, W + p.o_R11, W + p.o_Rinv, pivw, flag);
+        else
+            k_pivchol<false><<<1, nthr, 0, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, W + p.o_R11, W + p.o_Rinv, pivw, flag);
         TK_LAUNCH_CHECK("k_pivchol");
-        k_q1_gram<YT><<<(unsigned)p.nblk2, 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_Rinv, flag, W + p.o_part2);
+        k_q1_gram<YT><<<(unsigned)p.nblk2, 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_Rinv, W + p.o_part2);
         TK_LAUNCH_CHECK("k_q1_gram");
-        k_sum_partials<<<(unsigned)(p.R * p.R), 256, 0, s>>>(W + p.o_part2, p.nblk2, p.R * p.R, flag, W + p.o_G2);
+        k_sum_partials<<<(unsigned)(p.R * p.R), 256, 0, s>>>(W + p.o_part2, p.nblk2, p.R * p.R, nullptr, W + p.o_G2);
         TK_LAUNCH_CHECK("k_sum_partials");
-        k_qrp_finish<YT><<<1, 256, 0, s>>>(Y, p.n, p.R, pivw, W + p.o_Rinv, W + p.o_G2, flag, W + p.o_M, piv);
+#define TK_FINISH(RM, EX) \
+    k_qrp_finish<YT, RM, EX><<<1, 64, 0, s>>>(Y, p.n, p.R, pivw, W + p.o_Rinv, W + p.o_G2, flag, W + p.o_M, piv)
+        if (p.R == 16) TK_FINISH(16, true);
+        else if (p.R == 8) TK_FINISH(8, true);
+        else if (p.R < 16) TK_FINISH(16, false);
+        else if (p.R == 32) TK_FINISH(32, true);
+        else TK_FINISH(32, false);
+#undef TK_FINISH
         TK_LAUNCH_CHECK("k_qrp_finish");
-        k_form_u<YT, LT><<<cdiv(p.m * ldlp, 256), 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_M, flag, U, Ulp, ldlp);
+        // U = Y[:, piv] M, or (flag set) the Householder fallback on Y in workgroup 0
+        k_form_u<YT, LT><<<cdiv(p.m * ldlp, 256), 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_M, flag, U, Ulp, ldlp,
+                                                             W + p.o_A, W + p.o_V, W + p.o_w, W + p.o_beta, perm, piv);
         TK_LAUNCH_CHECK("k_form_u");
-        // fallback, gated on the flag
-        k_house_qrp<YT, LT><<<1, 1024, 0, s>>>(Y, W + p.o_A, I, (int)K, p.R, W + p.o_V, W + p.o_w, W + p.o_beta, perm, flag, 1, U,
-                                           Ulp, ldlp, piv);
-        TK_LAUNCH_CHECK("k_house_qrp");
         return TK_OK;
     }
     if (p.route == 2) {
         k_syrk_rows<YT><<<cdiv(I * I, 256), 256, 0, s>>>(Y, (int)I, (int)K, W + p.o_A);
         TK_LAUNCH_CHECK("k_syrk_rows");
     }
-    k_house_qrp<YT, LT><<<1, 1024, 0, s>>>(p.route == 2 ? nullptr : Y, W + p.o_A, p.m, p.n, p.R, W + p.o_V, W + p.o_w, W + p.o_beta, perm, nullptr, 0, U,
-                                       Ulp, ldlp, piv);
+    k_house_qrp<YT, LT><<<1, 1024, 0, s>>>(p.route == 2 ? nullptr : Y, W + p.o_A, p.m, p.n, p.R, W + p.o_V, W + p.o_w,
+                                           W + p.o_beta, perm, U, Ulp, ldlp, piv);
     TK_LAUNCH_CHECK("k_house_qrp");
     return TK_OK;
 }
