@@ -21,6 +21,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
+# rocprofv3 FETCH_SIZE / WRITE_SIZE counters of the dominant kernel on this workload, with the
+# source hash of the kernel file they were taken on (traffic is reported only while it matches)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_ttmc3_lds_f32_lowrank_10000cube_10M_r16.md")
+TTMC_SOURCE = os.path.join(ROOT, "paper_2010_10638_amd", "csrc", "ttmc.hip")
 
 
 def alg_bytes_ttmc(ctx, info, nnz, mode, val_bytes, fac_bytes, y_bytes):
@@ -53,6 +57,70 @@ def cpu_baseline(w, budget_s=10.0):
                        f"single-threaded FP64 C oracle, {dt:.1f} s")
 
 
+def _sha256(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per TTMc launch from the committed counter summary, or None when the summary is
+    missing or was taken on another version of the kernel source."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    sha = traffic = None
+    with open(TRAFFIC_PROFILE) as f:
+        for line in f:
+            if line.startswith("ttmc.hip sha256:"):
+                sha = line.split(":", 1)[1].strip()
+            elif line.startswith("traffic bytes per launch:"):
+                traffic = float(line.split(":", 1)[1].strip())
+    if sha is None or traffic is None or sha != _sha256(TTMC_SOURCE):
+        return None
+    return traffic
+
+
+def _csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_trace(d):
+    """Markdown table of a rocprofv3 --kernel-trace --stats output directory (run_kernel_stats.csv)."""
+    rows = _csv(os.path.join(d, "run_kernel_stats.csv"))
+    out = ["| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
+    for r in rows[:30]:
+        out.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def _counter_mean(d, counter, name_sub):
+    vals = [float(r["Counter_Value"]) for r in _csv(os.path.join(d, "run_counter_collection.csv"))
+            if r["Counter_Name"] == counter and name_sub in r["Kernel_Name"]]
+    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE of `kernel`, calibrated by a 512 MiB device copy."""
+    fk, nf = _counter_mean(fetch_dir, "FETCH_SIZE", kernel)
+    wk, nw = _counter_mean(write_dir, "WRITE_SIZE", kernel)
+    cf, _ = _counter_mean(copy_fetch_dir, "FETCH_SIZE", "copyBuffer")
+    cw, _ = _counter_mean(copy_write_dir, "WRITE_SIZE", "copyBuffer")
+    copy_kib = (128 << 20) * 4 / 1024
+    ff, fw = copy_kib / cf, copy_kib / cw
+    traffic = (fk * ff + wk * fw) * 1024
+    return "\n".join([
+        f"FETCH_SIZE per dispatch (KiB): {fk:.1f} over {nf} dispatches",
+        f"WRITE_SIZE per dispatch (KiB): {wk:.1f} over {nw} dispatches",
+        f"copy calibration: 524288 KiB read and written per copy; FETCH_SIZE reads {cf:.1f} KiB "
+        f"(factor {ff:.3f}), WRITE_SIZE reads {cw:.1f} KiB (factor {fw:.3f})",
+        f"traffic bytes per launch: {traffic:.0f}",
+        f"ttmc.hip sha256: {_sha256(TTMC_SOURCE)}",
+    ])
+
+
 def _K(ranks, n):
     k = 1
     for t, r in enumerate(ranks):
@@ -70,7 +138,18 @@ def main():
     ap.add_argument("--small", action="store_true", help="small tensor (for profiling dry runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (calibrates FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--summarize-trace", metavar="DIR", help="print a markdown summary of a rocprofv3 "
+                    "--kernel-trace --stats output directory and exit")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="print the calibrated per-launch HBM traffic of the TTMc kernel from four "
+                    "rocprofv3 --pmc output directories and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return
+    if args.summarize_pmc:
+        print(summarize_pmc(*args.summarize_pmc, kernel="k_ttmc3_lds<float>"))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the TTMc and QRP would shard).", file=sys.stderr)
@@ -112,16 +191,19 @@ def main():
     for _ in range(args.warmup):
         tk.hooi_sweep(ctx, U, G, fit)
     torch.cuda.synchronize()
-    tk.tucker_profile(ctx, args.steps)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         tk.hooi_sweep(ctx, U, G, fit)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    print(f"# timed {args.steps} sweeps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
+    # the same number of sweeps again with HIP events on the sweep's stream around every region
+    # and around each main TTMc kernel (breakdown and roofline; not part of the timed value)
+    tk.tucker_profile(ctx, args.steps)
+    for _ in range(args.steps):
+        tk.hooi_sweep(ctx, U, G, fit)
     prof = tk.tucker_profile_read(ctx)
     tk.tucker_profile(ctx, 0)
-    print(f"# timed {args.steps} sweeps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
 
     N = len(w.dims)
     nnz = info["nnz"]
@@ -134,10 +216,11 @@ def main():
     fac_bytes = val_bytes
     y_bytes = 8 if w.dtype == "f64" else 4
     ttmc_s = sum(prof["ttmc_ms"]) / 1e3 / prof["sweeps"]          # per sweep, all modes
+    kern_s = sum(prof["ttmc_kernel_ms"]) / 1e3 / prof["sweeps"]   # main kernel only
     launches = N
     flops = sum(2 * nnz * _K(w.ranks, n) for n in range(N)) / launches
     bytes_ = sum(alg_bytes_ttmc(ctx, info, nnz, n, val_bytes, fac_bytes, y_bytes) for n in range(N)) / launches
-    t_launch = ttmc_s / launches
+    t_launch = kern_s / launches
     tflops = flops / t_launch / 1e12
     gbs = bytes_ / t_launch / 1e9
     qrp_s = sum(prof["qrp_ms"]) / 1e3 / prof["sweeps"]
@@ -159,8 +242,8 @@ def main():
         "config": {"workload": w.name, "dims": w.dims, "ranks": w.ranks, "nnz": nnz,
                    "ttmc": w.dtype, "qrp": "f64", "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
-                     "kernel": "k_ttmc3_mfma<float,float>",
+                     "frac": tflops / PEAK_FP32_MFMA_TFLOPS, "traffic": measured_traffic(),
+                     "kernel": "k_ttmc3_lds<float>",
                      "flops_per_launch": flops, "alg_bytes_per_launch": bytes_,
                      "avg_launch_ms": t_launch * 1e3,
                      "hbm_gbs_alg": gbs, "hbm_frac_alg": gbs / PEAK_HBM_GBS},

@@ -170,10 +170,14 @@ int tucker_profile(tk_ctx* ctx, int capacity);
 /*
  * tucker_profile_read - synchronise the recorded events and return the summed region times in
  * milliseconds since tucker_profile was switched on (host outputs, any may be NULL):
- *   ttmc_ms  double[N]   per-mode TTMc time     qrp_ms  double[N]   per-mode QRP time
- *   core_ms  double      core and fit           sweeps  int64       sweeps recorded
+ *   ttmc_ms         double[N]  per-mode TTMc region (main kernel and split-row fix-up)
+ *   ttmc_kernel_ms  double[N]  per-mode main TTMc kernel alone
+ *   qrp_ms          double[N]  per-mode QRP time
+ *   core_ms         double     core and fit
+ *   sweeps          int64      sweeps recorded
  */
-int tucker_profile_read(tk_ctx* ctx, double* ttmc_ms, double* qrp_ms, double* core_ms, int64_t* sweeps);
+int tucker_profile_read(tk_ctx* ctx, double* ttmc_ms, double* ttmc_kernel_ms, double* qrp_ms, double* core_ms,
+                        int64_t* sweeps);
 
 /* tucker_free - synchronise the last stream used, release every context allocation.  NULL is ok. */
 void tucker_free(tk_ctx* ctx);

@@ -53,7 +53,7 @@ def load_library(path: str = LIB_PATH):
     lib.hooi_sweep.argtypes = [P, P, P, P, P, P]
     lib.reconstruct.argtypes = [P, P, P, I64, P, P, P]
     lib.tucker_profile.argtypes = [P, I]
-    lib.tucker_profile_read.argtypes = [P, P, P, P, P]
+    lib.tucker_profile_read.argtypes = [P, P, P, P, P, P]
     lib.tucker_free.argtypes = [P]
     lib.tucker_free.restype = None
     lib.tucker_last_error.restype = ctypes.c_char_p
@@ -234,11 +234,12 @@ def tucker_profile(ctx: Ctx, capacity: int):
 def tucker_profile_read(ctx: Ctx) -> dict:
     N = ctx.order
     tt = (ctypes.c_double * N)()
+    tk = (ctypes.c_double * N)()
     qq = (ctypes.c_double * N)()
     cc = ctypes.c_double()
     ns = ctypes.c_int64()
-    _check(load_library().tucker_profile_read(ctx.handle, tt, qq, ctypes.byref(cc), ctypes.byref(ns)))
-    return dict(ttmc_ms=list(tt), qrp_ms=list(qq), core_ms=cc.value, sweeps=ns.value)
+    _check(load_library().tucker_profile_read(ctx.handle, tt, tk, qq, ctypes.byref(cc), ctypes.byref(ns)))
+    return dict(ttmc_ms=list(tt), ttmc_kernel_ms=list(tk), qrp_ms=list(qq), core_ms=cc.value, sweeps=ns.value)
 
 
 def tucker_free(ctx: Ctx):

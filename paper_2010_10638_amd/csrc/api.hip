@@ -251,13 +251,15 @@ int hooi_sweep(tk_ctx* ctx, double* const* U, double* G, double* fit_dev, double
     for (int t = 1; t < ctx->N; ++t)
         if ((st = convert_factor(ctx, t, U[t], s))) return st;
     double* fit = (fit_dev || !fit_host) ? fit_dev : ctx->ws.scal;
-    // events: [ttmc start, ttmc end = qrp start] per mode, then qrp end of the last mode, core end
+    // events: [ttmc start, ttmc end = qrp start] per mode, then qrp end of the last mode, core end,
+    // then [main TTMc kernel start, end] per mode
+    const int N = ctx->N;
     hipEvent_t* ev = nullptr;
     if (ctx->prof_ev && ctx->prof_used < ctx->prof_cap)
-        ev = ctx->prof_ev + (size_t)(ctx->prof_used++) * (2 * ctx->N + 2);
+        ev = ctx->prof_ev + (size_t)(ctx->prof_used++) * (4 * N + 2);
     for (int n = 0; n < ctx->N; ++n) {
         if (ev) TK_HIP(hipEventRecord(ev[2 * n], s));
-        if ((st = ttmc_run(ctx, n, ctx->ws.y, s))) return st;
+        if ((st = ttmc_run(ctx, n, ctx->ws.y, s, ev ? ev + 2 * N + 2 + 2 * n : nullptr))) return st;
         if (ev) TK_HIP(hipEventRecord(ev[2 * n + 1], s));
         if ((st = qrp_run(ctx, n, ctx->ws.y, U[n], nullptr, s))) return st;
     }
@@ -294,18 +296,19 @@ int tucker_profile(tk_ctx* ctx, int capacity) {
     if (ctx->last_stream || ctx->prof_ev) (void)hipStreamSynchronize(ctx->last_stream);
     free_events(ctx);
     if (capacity == 0) return TK_OK;
-    const int per = 2 * ctx->N + 2;
+    const int per = 4 * ctx->N + 2;
     ctx->prof_ev = new hipEvent_t[(size_t)capacity * per]();
     ctx->prof_cap = capacity;
     for (int i = 0; i < capacity * per; ++i) TK_HIP(hipEventCreate(&ctx->prof_ev[i]));
     return TK_OK;
 }
 
-int tucker_profile_read(tk_ctx* ctx, double* ttmc_ms, double* qrp_ms, double* core_ms, int64_t* sweeps) {
+int tucker_profile_read(tk_ctx* ctx, double* ttmc_ms, double* ttmc_kernel_ms, double* qrp_ms, double* core_ms,
+                        int64_t* sweeps) {
     int st = check_ctx(ctx);
     if (st) return st;
-    const int N = ctx->N, per = 2 * N + 2;
-    double tt[kMaxOrder] = {}, qq[kMaxOrder] = {}, cc = 0.0;
+    const int N = ctx->N, per = 4 * N + 2;
+    double tt[kMaxOrder] = {}, tk_[kMaxOrder] = {}, qq[kMaxOrder] = {}, cc = 0.0;
     for (int k = 0; k < ctx->prof_used; ++k) {
         hipEvent_t* ev = ctx->prof_ev + (size_t)k * per;
         TK_HIP(hipEventSynchronize(ev[per - 1]));
@@ -315,12 +318,15 @@ int tucker_profile_read(tk_ctx* ctx, double* ttmc_ms, double* qrp_ms, double* co
             tt[n] += ms;
             TK_HIP(hipEventElapsedTime(&ms, ev[2 * n + 1], (n + 1 < N) ? ev[2 * n + 2] : ev[2 * N]));
             qq[n] += ms;
+            TK_HIP(hipEventElapsedTime(&ms, ev[2 * N + 2 + 2 * n], ev[2 * N + 3 + 2 * n]));
+            tk_[n] += ms;
         }
         TK_HIP(hipEventElapsedTime(&ms, ev[2 * N], ev[2 * N + 1]));
         cc += ms;
     }
     for (int n = 0; n < N; ++n) {
         if (ttmc_ms) ttmc_ms[n] = tt[n];
+        if (ttmc_kernel_ms) ttmc_kernel_ms[n] = tk_[n];
         if (qrp_ms) qrp_ms[n] = qq[n];
     }
     if (core_ms) *core_ms = cc;

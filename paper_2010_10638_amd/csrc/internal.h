@@ -170,7 +170,8 @@ int convert_factor(tk_ctx* ctx, int k, const double* U, hipStream_t s);
 int fill_zero(void* p, size_t bytes, hipStream_t s);
 
 // TTMc (ttmc.hip): uses ctx->Ulp copies
-int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s);
+// ev_main (optional, [2]): events recorded on s around the main TTMc kernel (fix-up excluded)
+int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main = nullptr);
 
 // QRP (qrp.hip): Y -> U (FP64) and the low-precision copy ctx->Ulp[mode]
 int qrp_run(tk_ctx* ctx, int mode, const void* Y, double* U, int32_t* piv, hipStream_t s);

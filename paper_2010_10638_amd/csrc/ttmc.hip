@@ -474,12 +474,17 @@ int launch_generic(const TtmcArgs& a, hipStream_t s) {
 
 }  // namespace
 
-int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s) {
+int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main) {
     const ModeLayout& ml = ctx->mode[mode];
     const int N = ctx->N;
     const int64_t In = ctx->dims[mode];
     const size_t ysz = ytype_size(ctx->dtype);
-    if (ml.nchunks == 0) return fill_zero(Y, (size_t)In * ml.K * ysz, s);
+    if (ml.nchunks == 0) {
+        if (ev_main) TK_HIP(hipEventRecord(ev_main[0], s));
+        const int st0 = fill_zero(Y, (size_t)In * ml.K * ysz, s);
+        if (ev_main) TK_HIP(hipEventRecord(ev_main[1], s));
+        return st0;
+    }
     TtmcArgs a{};
     a.chunk_ptr = ml.chunk_ptr;
     a.chunk_row = ml.chunk_row;
@@ -506,6 +511,7 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s) {
     }
     const unsigned grid = (unsigned)((ml.nchunks + 3) / 4);
     int st = TK_OK;
+    if (ev_main) TK_HIP(hipEventRecord(ev_main[0], s));
     if (mfma_ok) {
         if (ctx->dtype == TK_F64) {
             k_ttmc3_mfma<double, double><<<grid, 256, 0, s>>>(a);
@@ -523,6 +529,7 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s) {
         else st = launch_generic<float, bf16_t>(a, s);
         if (st) return st;
     }
+    if (ev_main) TK_HIP(hipEventRecord(ev_main[1], s));
     if (ml.nsplit > 0) {
         if (ctx->dtype == TK_F64)
             k_ttmc_fixup<double><<<(unsigned)ml.nsplit, 256, 0, s>>>(ml.split, ml.rows, (int)ml.K,
