@@ -121,6 +121,73 @@ def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel):
     ])
 
 
+def ttmc_kernel_name(w):
+    if len(w.dims) == 3 and max(w.ranks) <= 16:
+        return {"f64": "k_ttmc3_mfma<double,double>", "f32": "k_ttmc3_lds<float>", "bf16": "k_ttmc3_lds<bf16>"}[w.dtype]
+    if len(w.dims) >= 4:
+        return "k_ttmc_fiber"
+    return "k_ttmc_generic"
+
+
+def roofline(w, N, flops, bytes_, t_launch, default):
+    """Roofline object of the dominant kernel.  The bench workload's TTMc does 2*K_n flops per
+    12 bytes of stream (intensity ~39 flop/B, above the FP32 ridge of 19.7): MFMA-bound; the
+    skewed and order-4 (fiber-factored) TTMcs are HBM-bound; the FP64 200^3 case is latency-bound
+    and reported against FP64 MFMA."""
+    gbs = bytes_ / t_launch / 1e9
+    tflops = flops / t_launch / 1e12
+    common = {"kernel": ttmc_kernel_name(w), "flops_per_launch": flops, "alg_bytes_per_launch": bytes_,
+              "avg_launch_ms": t_launch * 1e3, "hbm_gbs_alg": gbs, "hbm_frac_alg": gbs / PEAK_HBM_GBS}
+    if w.dtype == "f64":
+        return {"bound": "mfma", "achieved": tflops, "peak": 78.6, "unit": "TFLOP/s", "frac": tflops / 78.6,
+                "traffic": None, **common}
+    if flops / bytes_ > PEAK_FP32_MFMA_TFLOPS / (PEAK_HBM_GBS / 1e3) and N == 3:
+        return {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": tflops / PEAK_FP32_MFMA_TFLOPS, "traffic": measured_traffic() if default else None, **common}
+    return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "traffic": None, **common}
+
+
+def run_completion(args, w, tk, torch):
+    """One step = the completion loss and its gradients (adjoint TTMc over every mode) and one
+    Adam update of the core and the factors, on the 30M-entry workload."""
+    coords = torch.from_numpy(w.coords).cuda()
+    vals = torch.from_numpy(w.vals).cuda()
+    ctx = tk.tucker_init(coords, vals, w.dims, w.ranks, dtype="f32")
+    del coords, vals
+    nnz = tk.tucker_get_info(ctx)["nnz"]
+    G = torch.from_numpy(w.G_init).float().cuda().requires_grad_()
+    U = [torch.from_numpy(u).float().cuda().requires_grad_() for u in w.U_init]
+    opt = torch.optim.Adam([G] + U, lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+
+    def step():
+        opt.zero_grad()
+        loss = tk.completion_loss(ctx, G, U)
+        loss.backward()
+        opt.step()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    N = len(w.dims)
+    upd = sum(nnz * _K(w.ranks, n) for n in range(N))
+    dt = (t1 - t0) / args.steps
+    out = {"metric": "adjoint TTMc nnz*prod(R) updates/s over whole completion steps (loss, gradients, Adam)",
+           "value": upd / dt, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "dims": w.dims, "ranks": w.ranks, "nnz": nnz, "optimizer": "adam",
+                      "parallelism": "single-gpu"},
+           "loss": float(loss.item())}
+    print(json.dumps(out), flush=True)
+
+
 def _K(ranks, n):
     k = 1
     for t, r in enumerate(ranks):
@@ -136,6 +203,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="small tensor (for profiling dry runs)")
+    ap.add_argument("--workload", default="lowrank",
+                    choices=["lowrank", "hooi200", "skewed-f32", "skewed-bf16", "order4-f32", "order4-bf16",
+                             "completion"],
+                    help="lowrank (default): 10,000^3, 10M nnz, R 16, FP32 TTMc; hooi200: 200^3, 20,000 nnz, "
+                    "R 8, FP64; skewed-*: 500,000 x 100,000 x 365, 50M Zipf nnz, R 10; order4-*: "
+                    "50,000 x 50,000 x 5,000 x 100, 20M nnz, R 8; completion: 100,000 x 100,000 x 1,000, "
+                    "30M entries, R 16, one Adam step of the completion loss per step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (calibrates FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a markdown summary of a rocprofv3 "
@@ -175,10 +249,20 @@ def main():
     t_gen = time.perf_counter()
     if args.small:
         w = synth.lowrank_f32(dims=(2000, 2000, 2000), nnz=1_000_000)
-    else:
+    elif args.workload == "lowrank":
         w = synth.lowrank_f32()
+    elif args.workload == "hooi200":
+        w = synth.hooi_small_f64()
+    elif args.workload.startswith("skewed"):
+        w = synth.skewed(dtype=args.workload.split("-")[1])
+    elif args.workload.startswith("order4"):
+        w = synth.order4(dtype=args.workload.split("-")[1])
+    else:
+        w = synth.completion()
     print(f"# generated {w.name} in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
+    if args.workload == "completion" and not args.small:
+        return run_completion(args, w, tk, torch)
     coords = torch.from_numpy(w.coords).cuda()
     vals = torch.from_numpy(w.vals).cuda()
     ctx = tk.tucker_init(coords, vals, w.dims, w.ranks, dtype=w.dtype)
@@ -212,6 +296,7 @@ def main():
     value = upd_per_sweep / sweep_s
 
     # dominant kernel: the TTMc (one launch per mode per sweep)
+    default = args.workload == "lowrank" and not args.small
     val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[w.dtype]
     fac_bytes = val_bytes
     y_bytes = 8 if w.dtype == "f64" else 4
@@ -237,23 +322,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": w.dtype,
         "data": "synthetic",
         "config": {"workload": w.name, "dims": w.dims, "ranks": w.ranks, "nnz": nnz,
                    "ttmc": w.dtype, "qrp": "f64", "parallelism": "single-gpu"},
-        "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / PEAK_FP32_MFMA_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "k_ttmc3_lds<float>",
-                     "flops_per_launch": flops, "alg_bytes_per_launch": bytes_,
-                     "avg_launch_ms": t_launch * 1e3,
-                     "hbm_gbs_alg": gbs, "hbm_frac_alg": gbs / PEAK_HBM_GBS},
+        "roofline": roofline(w, N, flops, bytes_, t_launch, default),
         "breakdown_ms_per_sweep": {"ttmc": ttmc_s * 1e3, "qrp": qrp_s * 1e3, "core_fit": core_s * 1e3,
                                    "ttmc_per_mode": [x / prof["sweeps"] for x in prof["ttmc_ms"]],
+                                   "ttmc_kernel_per_mode": [x / prof["sweeps"] for x in prof["ttmc_kernel_ms"]],
                                    "qrp_per_mode": [x / prof["sweeps"] for x in prof["qrp_ms"]]},
         "ttmc_updates_per_s": upd_per_sweep / ttmc_s,
         "fit": float(fit.item()),
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and default:
         out["cpu_baseline"] = cpu_baseline(w)
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
     print(json.dumps(out), flush=True)

@@ -159,6 +159,30 @@ int reconstruct(tk_ctx* ctx, const double* G, const double* const* U, int64_t m,
                 const int32_t* coords, double* out, void* stream);
 
 /*
+ * ttmc_adjoint - loss and gradients of the sampled-entry Tucker model over the context's entries
+ * (Tucker completion, built on the adjoint of the TTMc of Alg. 2).  With the model value
+ * xhat_p = sum_r G[r] prod_k U_k(i_k, r_k) and the residual e_p = xhat_p - x_p of every entry p
+ * of the context (|Omega| = distinct entries):
+ *   loss  = sum_p e_p^2 / (2 |Omega|)
+ *   gU_n  = E_(n) (kron_{k != n} U_k) G_(n)^T / |Omega|        (I_n x R_n)
+ *   gG    = sum_p e_p kron_k U_k(i_k, :) / |Omega|             (C order, like G)
+ *   dtype  TK_F32 or TK_F64: the type of G, U, loss, gG, gU; it must equal the context's TTMc
+ *          type (a TK_BF16 context returns TK_ERR_UNSUPPORTED)
+ *   G      device [prod R_k], C order (last mode fastest)
+ *   U      host array of N device pointers, I_k x R_k row-major
+ *   loss   device scalar
+ *   gG     device [prod R_k], written
+ *   gU     host array of N device pointers, I_k x R_k, written
+ * Every pointer is caller-owned; the work is enqueued on `stream` without synchronisation.  The
+ * first call allocates the completion workspace (the row of every padded position of each mode,
+ * one mode's residuals, U_n G_(n)), held until tucker_free.  Sums run in a fixed order, so the
+ * results are deterministic.  Errors: TK_ERR_ARG (null pointer, dtype mismatch),
+ * TK_ERR_UNSUPPORTED, TK_ERR_OOM, TK_ERR_HIP.
+ */
+int ttmc_adjoint(tk_ctx* ctx, int dtype, const void* G, const void* const* U, void* loss, void* gG,
+                 void* const* gU, void* stream);
+
+/*
  * tucker_profile - start (capacity > 0) or stop (capacity = 0) timing the regions of hooi_sweep.
  * While on, each sweep records HIP events on its stream around every mode's TTMc (kernel and
  * split-row fix-up), every QRP and the core/fit; at most `capacity` sweeps are recorded.  The

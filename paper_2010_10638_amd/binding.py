@@ -21,7 +21,7 @@ DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
 _STATUS = {1: "TK_ERR_ARG", 2: "TK_ERR_RANGE", 3: "TK_ERR_OOM", 4: "TK_ERR_HIP", 5: "TK_ERR_UNSUPPORTED"}
 
 EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "core_fit",
-           "hooi_sweep", "reconstruct", "tucker_profile", "tucker_profile_read", "tucker_free",
+           "hooi_sweep", "reconstruct", "ttmc_adjoint", "tucker_profile", "tucker_profile_read", "tucker_free",
            "tucker_last_error")
 
 
@@ -52,6 +52,7 @@ def load_library(path: str = LIB_PATH):
     lib.core_fit.argtypes = [P, P, P, P, P, P]
     lib.hooi_sweep.argtypes = [P, P, P, P, P, P]
     lib.reconstruct.argtypes = [P, P, P, I64, P, P, P]
+    lib.ttmc_adjoint.argtypes = [P, I, P, P, P, P, P, P]
     lib.tucker_profile.argtypes = [P, I]
     lib.tucker_profile_read.argtypes = [P, P, P, P, P, P]
     lib.tucker_free.argtypes = [P]
@@ -225,6 +226,41 @@ def reconstruct(ctx: Ctx, G: torch.Tensor, U, coords: torch.Tensor, out: torch.T
                                       _dev(coords, torch.int32, "coords"), _dev(out, torch.float64, "out"),
                                       _stream()))
     return out
+
+
+def ttmc_adjoint(ctx: Ctx, G: torch.Tensor, U, loss=None, gG=None, gU=None):
+    """Loss and gradients of the sampled-entry Tucker model over ctx's entries (completion).
+
+    G: [R_1, ..., R_N] and U[k]: [I_k, R_k], in the context's TTMc type (float32 for an "f32"
+    context, float64 for "f64").  Returns (loss [1], gG like G, [gU_k like U_k])."""
+    lib = load_library()
+    if ctx.dtype not in ("f32", "f64"):
+        raise TuckerError(TK_ERR_UNSUPPORTED, "ttmc_adjoint needs an f32 or f64 context")
+    dt = ctx.ytype
+    N = ctx.order
+    if loss is None:
+        loss = torch.empty(1, dtype=dt, device="cuda")
+    if gG is None:
+        gG = torch.empty(ctx.ranks, dtype=dt, device="cuda")
+    if gU is None:
+        gU = [torch.empty((ctx.dims[k], ctx.ranks[k]), dtype=dt, device="cuda") for k in range(N)]
+    for k in range(N):
+        if tuple(U[k].shape) != (ctx.dims[k], ctx.ranks[k]) or tuple(gU[k].shape) != (ctx.dims[k], ctx.ranks[k]):
+            raise ValueError(f"U[{k}] / gU[{k}] must be {ctx.dims[k]} x {ctx.ranks[k]}")
+    if G.numel() != gG.numel() or G.numel() != _prod(ctx.ranks):
+        raise ValueError("G / gG must hold prod(ranks) values")
+    up = (ctypes.c_void_p * N)(*[_dev(U[k], dt, f"U[{k}]").value for k in range(N)])
+    gp = (ctypes.c_void_p * N)(*[_dev(gU[k], dt, f"gU[{k}]").value for k in range(N)])
+    _check(lib.ttmc_adjoint(ctx.handle, DTYPES[ctx.dtype], _dev(G, dt, "G"), up, _dev(loss, dt, "loss"),
+                            _dev(gG, dt, "gG"), gp, _stream()))
+    return loss, gG, gU
+
+
+def _prod(xs):
+    p = 1
+    for x in xs:
+        p *= int(x)
+    return p
 
 
 def tucker_profile(ctx: Ctx, capacity: int):

@@ -43,7 +43,7 @@ int dmalloc(void** p, size_t bytes) {
 
 void free_events(tk_ctx* c) {
     if (c->prof_ev) {
-        const int per = 2 * c->N + 2;
+        const int per = 4 * c->N + 2;
         for (int i = 0; i < c->prof_cap * per; ++i)
             if (c->prof_ev[i]) (void)hipEventDestroy(c->prof_ev[i]);
         delete[] c->prof_ev;
@@ -56,6 +56,7 @@ void free_events(tk_ctx* c) {
 void free_ctx(tk_ctx* c) {
     if (!c) return;
     free_events(c);
+    free_completion_ws(c);
     for (int m = 0; m < kMaxOrder; ++m) {
         ModeLayout& ml = c->mode[m];
         void* ps[] = {ml.rows, ml.ptr, ml.pptr, ml.idx, ml.val, ml.chunk_ptr, ml.chunk_row, ml.chunk_slot, ml.split};
@@ -285,6 +286,23 @@ int reconstruct(tk_ctx* ctx, const double* G, const double* const* U, int64_t m,
     if ((st = pending_error())) return st;
     hipStream_t s = (hipStream_t)stream;
     st = reconstruct_run(ctx, G, U, m, coords, out, s);
+    ctx->last_stream = s;
+    return st;
+}
+
+int ttmc_adjoint(tk_ctx* ctx, int dtype, const void* G, const void* const* U, void* loss, void* gG,
+                 void* const* gU, void* stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (ctx->dtype == TK_BF16) return set_error(TK_ERR_UNSUPPORTED, "ttmc_adjoint needs an FP32 or FP64 context");
+    if (dtype != ctx->dtype)
+        return set_error(TK_ERR_ARG, "dtype %d differs from the context's TTMc type %d", dtype, ctx->dtype);
+    if (!G || !U || !loss || !gG || !gU) return set_error(TK_ERR_ARG, "null argument");
+    for (int t = 0; t < ctx->N; ++t)
+        if (!U[t] || !gU[t]) return set_error(TK_ERR_ARG, "U[%d] or gU[%d] is null", t, t);
+    if ((st = pending_error())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = adjoint_run(ctx, G, U, loss, gG, gU, s);
     ctx->last_stream = s;
     return st;
 }

@@ -1,0 +1,389 @@
+// Tucker completion: loss and gradients of a sampled-entry Tucker model, built on the adjoint of
+// the sparse TTMc (spec addition to the method of Alg. 2).
+//
+// For observed entries p in Omega with values x_p:
+//   xhat_p = sum_r G[r] prod_k U_k(i_k, r_k),   e_p = xhat_p - x_p,   L = sum_p e_p^2 / (2 |Omega|)
+//   dL/dU_n   = TTMc_n(E) G_(n)^T / |Omega|        (TTMc_n(E) = E_(n) kron_{k != n} U_k, I_n x K_n)
+//   dL/dG_(N) = U_N^T TTMc_N(E) / |Omega|
+// where E is the sparse tensor of residuals on the pattern of X.  Per mode n the residuals are
+// computed on mode n's own sorted stream: with W_n = U_n G_(n) (I_n x K_n, dense), the model value
+// of an entry is the dot product of row i_n of W_n with the entry's Kronecker row, so no
+// permutation between the modes' orders is needed.  The residual values then replace the tensor
+// values in the ordinary TTMc kernels (the adjoint reuses the forward kernels unchanged), and two
+// small dense products give the gradients.  All sums have a fixed order: results are
+// deterministic.
+#include "internal.h"
+#include "atb.h"
+
+namespace tk {
+
+namespace {
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// rowid[q] = compressed row holding padded position q (binary search of the padded pointers)
+__global__ void k_rowid(const int32_t* __restrict__ pptr, int64_t S, int64_t P, int32_t* __restrict__ rowid) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    int64_t lo = 0, hi = S - 1;   // largest s with pptr[s] <= q
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (pptr[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    rowid[q] = (int32_t)lo;
+}
+
+// padded copy (I x ld, zero columns past R) of a factor given in the parameter type
+template <typename IT, typename LT>
+__global__ void k_factor_copy(const IT* __restrict__ U, int64_t I, int R, int ld, LT* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= I * ld) return;
+    const int64_t i = e / ld;
+    const int c = (int)(e % ld);
+    out[e] = (c < R) ? (LT)U[i * R + c] : (LT)0;
+}
+
+struct Unfold {
+    int32_t R[kMaxOrder];
+    int N;
+    int n;
+    int64_t K;
+    int64_t size;   // prod R
+};
+
+// Gn[r_n * K + c] = G[r_0, ..., r_{N-1}] (C order), c = the other modes' indices with the last
+// fastest: the mode-n unfolding in the Kronecker column order of the TTMc
+template <typename AT>
+__global__ void k_unfold(Unfold u, const AT* __restrict__ G, AT* __restrict__ Gn) {
+    const int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lin >= u.size) return;
+    int64_t rest = lin;
+    int digit[kMaxOrder];
+    for (int t = u.N - 1; t >= 0; --t) {
+        digit[t] = (int)(rest % u.R[t]);
+        rest /= u.R[t];
+    }
+    int64_t c = 0;
+    for (int t = 0; t < u.N; ++t)
+        if (t != u.n) c = c * u.R[t] + digit[t];
+    Gn[(int64_t)digit[u.n] * u.K + c] = G[lin];
+}
+
+// W[i][c] = sum_r U[i][r] Gn[r][c]   (r ascending)
+template <typename AT>
+__global__ void k_w(const AT* __restrict__ U, const AT* __restrict__ Gn, int64_t I, int R, int64_t K,
+                    AT* __restrict__ W) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= I * K) return;
+    const int64_t i = e / K, c = e % K;
+    AT acc = 0;
+    for (int r = 0; r < R; ++r) acc += U[i * R + r] * Gn[(int64_t)r * K + c];
+    W[e] = acc;
+}
+
+struct ResidArgs {
+    const int32_t* rowid;
+    const int32_t* rows;
+    const int32_t* ptr;      // unpadded row pointers
+    const int32_t* pptr;     // padded row pointers
+    const int32_t* idx;      // [nm1][P]
+    int64_t P;
+    const void* val;
+    const void* F[kMaxOrder - 1];
+    int32_t ld[kMaxOrder - 1];
+    int32_t R[kMaxOrder - 1];
+    int32_t nm1;
+    int64_t K;
+    const void* W;
+    void* e;                 // [P] residuals (pads: 0)
+    double* part;            // per-block sum of e^2, or null
+};
+
+// One padded entry per thread: e = W(i_n, :) . kron_p - x_p (0 on pads), the Kronecker row walked
+// in C order with an odometer that recomputes only the prefix products whose digit changed.
+template <typename AT>
+__global__ __launch_bounds__(256) void k_residual(ResidArgs a) {
+    __shared__ double red[4];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double e2 = 0.0;
+    if (q < a.P) {
+        const int s = a.rowid[q];
+        const bool real = (q - a.pptr[s]) < (int64_t)(a.ptr[s + 1] - a.ptr[s]);
+        AT ev = 0;
+        if (real) {
+            const int nm1 = a.nm1;
+            const AT* rowp[kMaxOrder - 1];
+            int r[kMaxOrder - 1];
+            AT pre[kMaxOrder];
+            for (int j = 0; j < nm1; ++j) {
+                int32_t t = a.idx[(int64_t)j * a.P + q];
+                if (j == 0) t &= kIndexMask;
+                rowp[j] = (const AT*)a.F[j] + (int64_t)t * a.ld[j];
+                r[j] = 0;
+            }
+            pre[0] = (AT)1;
+            for (int j = 0; j < nm1; ++j) pre[j + 1] = pre[j] * rowp[j][0];
+            const AT* w = (const AT*)a.W + (int64_t)a.rows[s] * a.K;
+            AT xh = 0;
+            for (int64_t c = 0; c < a.K; ++c) {
+                xh += w[c] * pre[nm1];
+                int j = nm1 - 1;
+                while (j >= 0) {
+                    if (++r[j] < a.R[j]) break;
+                    r[j] = 0;
+                    --j;
+                }
+                if (j < 0) break;
+                for (int u = j; u < nm1; ++u) pre[u + 1] = pre[u] * rowp[u][r[u]];
+            }
+            ev = xh - ((const AT*)a.val)[q];
+        }
+        ((AT*)a.e)[q] = ev;
+        e2 = (double)ev * (double)ev;
+    }
+    if (a.part) {
+        for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
+        __syncthreads();
+        if (threadIdx.x == 0) a.part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    }
+}
+
+// gU[i][r] = scale * sum_c Y[i][c] Gn[r][c]   (c ascending, FP64 accumulation)
+template <typename AT>
+__global__ void k_gu(const AT* __restrict__ Y, const AT* __restrict__ Gn, int64_t I, int R, int64_t K,
+                     double scale, AT* __restrict__ gU) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= I * R) return;
+    const int64_t i = e / R;
+    const int r = (int)(e % R);
+    double acc = 0.0;
+    for (int64_t c = 0; c < K; ++c) acc += (double)Y[i * K + c] * (double)Gn[(int64_t)r * K + c];
+    gU[e] = (AT)(scale * acc);
+}
+
+// part[split][r][c] = sum_{i in slab} U[i][r] Y[i][c] on FP64 MFMA (same blocking as the core)
+template <typename AT>
+__global__ __launch_bounds__(256) void k_gg_partial(const AT* __restrict__ Y, const AT* __restrict__ U,
+                                                    int64_t I, int K, int R, int64_t slab,
+                                                    double* __restrict__ part) {
+    __shared__ double As[2][32][65];
+    __shared__ double Bs[2][32][65];
+    const int b0 = blockIdx.x * 64, a0 = blockIdx.z * 64;
+    const int64_t r0 = (int64_t)blockIdx.y * slab;
+    const int64_t r1 = min(I, r0 + slab);
+    atb_d4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = atb_d4_t{0, 0, 0, 0};
+    atb_block<AT, AT>(U, R, R, Y, K, K, r0, r1, a0, b0, As, Bs, acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kq = lane >> 4, c16 = lane & 15;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = a0 + 16 * w + kq + 4 * v;
+            const int c = b0 + 16 * t + c16;
+            if (r < R && c < K) part[((int64_t)blockIdx.y * R + r) * K + c] = acc[t][v];
+        }
+}
+
+// gG[c * R + r] = scale * sum_split part[split][r][c]  (C order of the core: last mode = r)
+template <typename AT>
+__global__ void k_gg_reduce(const double* __restrict__ part, int nsplit, int K, int R, double scale,
+                            AT* __restrict__ gG) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)K * R) return;
+    const int r = (int)(e / K), c = (int)(e % K);
+    gG[(int64_t)c * R + r] = (AT)(scale * sum_strided(part + (int64_t)r * K + c, nsplit, (int64_t)R * K));
+}
+
+// loss = scale * sum_k part[k]: 1024 threads sum contiguous slices in order, then a fixed tree
+template <typename AT>
+__global__ __launch_bounds__(1024) void k_loss(const double* __restrict__ part, int64_t n, double scale,
+                                               AT* __restrict__ loss) {
+    __shared__ double red[1024];
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t b = (int64_t)threadIdx.x * per, e = min(n, b + per);
+    double s = 0.0;
+    for (int64_t k = b; k < e; ++k) s += part[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (AT)(scale * red[0]);
+}
+
+template <typename AT>
+__global__ void k_fill(AT* __restrict__ p, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = (AT)0;
+}
+
+void gg_plan(int64_t I, int64_t K, int R, int& nsplit, int64_t& slab) {
+    const int64_t cblocks = ((K + 63) / 64) * ((R + 63) / 64);
+    nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(cblocks, 1), (I + 127) / 128));
+    slab = ((I + nsplit - 1) / nsplit + 31) / 32 * 32;
+    nsplit = (int)((I + slab - 1) / slab);
+}
+
+int ensure_ws(tk_ctx* ctx, hipStream_t s) {
+    CompletionWs& w = ctx->cws;
+    if (w.ready) return TK_OK;
+    const int N = ctx->N;
+    const size_t at = ytype_size(ctx->dtype);
+    int64_t maxP = 0, maxIK = 0, gn = 0, part = 1024;
+    for (int n = 0; n < N; ++n) {
+        const ModeLayout& ml = ctx->mode[n];
+        maxP = std::max(maxP, ml.P);
+        maxIK = std::max<int64_t>(maxIK, ctx->dims[n] * ml.K);
+        gn += (int64_t)ctx->ranks[n] * ml.K;
+        part = std::max<int64_t>(part, (ml.P + 255) / 256);
+        int ns;
+        int64_t sl;
+        gg_plan(ctx->dims[n], ml.K, ctx->ranks[n], ns, sl);
+        part = std::max<int64_t>(part, (int64_t)ns * ctx->ranks[n] * ml.K);
+    }
+    auto alloc = [&](void** p, size_t bytes) -> int {
+        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return set_error(TK_ERR_OOM, "completion workspace: allocation of %zu bytes failed", bytes);
+        }
+        return TK_OK;
+    };
+    int st;
+    if ((st = alloc(&w.e, (size_t)maxP * at)) || (st = alloc(&w.W, (size_t)maxIK * at)) ||
+        (st = alloc(&w.Gn, (size_t)gn * at)) || (st = alloc((void**)&w.part, (size_t)part * 8)))
+        return st;
+    for (int n = 0; n < N; ++n) {
+        const ModeLayout& ml = ctx->mode[n];
+        if ((st = alloc((void**)&w.rowid[n], (size_t)ml.P * 4))) return st;
+        if (ml.P > 0) {
+            k_rowid<<<cdiv(ml.P, 256), 256, 0, s>>>(ml.pptr, ml.S, ml.P, w.rowid[n]);
+            TK_LAUNCH_CHECK("k_rowid");
+        }
+    }
+    w.ready = true;
+    return TK_OK;
+}
+
+template <typename AT>
+int adjoint_typed(tk_ctx* ctx, const AT* G, const AT* const* U, AT* loss, AT* gG, AT* const* gU, hipStream_t s) {
+    const int N = ctx->N;
+    int st;
+    if (ctx->nnz == 0) {   // empty pattern: zero loss and gradients
+        k_fill<AT><<<1, 64, 0, s>>>(loss, 1);
+        int64_t size = 1;
+        for (int t = 0; t < N; ++t) size *= ctx->ranks[t];
+        k_fill<AT><<<cdiv(size, 256), 256, 0, s>>>(gG, size);
+        for (int t = 0; t < N; ++t) {
+            const int64_t n = ctx->dims[t] * ctx->ranks[t];
+            k_fill<AT><<<cdiv(n, 256), 256, 0, s>>>(gU[t], n);
+        }
+        TK_LAUNCH_CHECK("k_fill");
+        return TK_OK;
+    }
+    if ((st = ensure_ws(ctx, s))) return st;
+    CompletionWs& w = ctx->cws;
+    const double scale = 1.0 / (double)ctx->nnz;
+    // low-precision factor copies read by the TTMc kernels (here in the parameter type)
+    for (int t = 0; t < N; ++t) {
+        const int64_t I = ctx->dims[t];
+        k_factor_copy<AT, AT><<<cdiv(I * ctx->ldU[t], 256), 256, 0, s>>>(U[t], I, ctx->ranks[t], ctx->ldU[t],
+                                                                          (AT*)ctx->Ulp[t]);
+        TK_LAUNCH_CHECK("k_factor_copy");
+    }
+    int64_t size = 1;
+    for (int t = 0; t < N; ++t) size *= ctx->ranks[t];
+    AT* Gn = (AT*)w.Gn;
+    int64_t nblk0 = 0;
+    for (int n = 0; n < N; ++n) {
+        const ModeLayout& ml = ctx->mode[n];
+        const int64_t I = ctx->dims[n];
+        const int R = ctx->ranks[n];
+        const int64_t K = ml.K;
+        Unfold u{};
+        for (int t = 0; t < N; ++t) u.R[t] = ctx->ranks[t];
+        u.N = N;
+        u.n = n;
+        u.K = K;
+        u.size = size;
+        k_unfold<AT><<<cdiv(size, 256), 256, 0, s>>>(u, G, Gn);
+        TK_LAUNCH_CHECK("k_unfold");
+        k_w<AT><<<cdiv(I * K, 256), 256, 0, s>>>(U[n], Gn, I, R, K, (AT*)w.W);
+        TK_LAUNCH_CHECK("k_w");
+        if (ml.P > 0) {
+            ResidArgs ra{};
+            ra.rowid = w.rowid[n];
+            ra.rows = ml.rows;
+            ra.ptr = ml.ptr;
+            ra.pptr = ml.pptr;
+            ra.idx = ml.idx;
+            ra.P = ml.P;
+            ra.val = ml.val;
+            for (int j = 0; j < N - 1; ++j) {
+                const int t = ml.others[j];
+                ra.F[j] = ctx->Ulp[t];
+                ra.ld[j] = ctx->ldU[t];
+                ra.R[j] = ctx->ranks[t];
+            }
+            ra.nm1 = N - 1;
+            ra.K = K;
+            ra.W = w.W;
+            ra.e = w.e;
+            ra.part = (n == 0) ? w.part : nullptr;
+            k_residual<AT><<<cdiv(ml.P, 256), 256, 0, s>>>(ra);
+            TK_LAUNCH_CHECK("k_residual");
+            if (n == 0) nblk0 = (ml.P + 255) / 256;
+        }
+        // TTMc_n(E): the forward kernels with the residuals in place of the values
+        if ((st = ttmc_run(ctx, n, ctx->ws.y, s, nullptr, w.e))) return st;
+        const AT* Y = (const AT*)ctx->ws.y;
+        k_gu<AT><<<cdiv(I * R, 256), 256, 0, s>>>(Y, Gn, I, R, K, scale, gU[n]);
+        TK_LAUNCH_CHECK("k_gu");
+        if (n == N - 1) {
+            int nsplit;
+            int64_t slab;
+            gg_plan(I, K, R, nsplit, slab);
+            dim3 grid(cdiv(K, 64), (unsigned)nsplit, cdiv(R, 64));
+            k_gg_partial<AT><<<grid, 256, 0, s>>>(Y, U[n], I, (int)K, R, slab, w.part);
+            TK_LAUNCH_CHECK("k_gg_partial");
+            k_gg_reduce<AT><<<cdiv(K * R, 256), 256, 0, s>>>(w.part, nsplit, (int)K, R, scale, gG);
+            TK_LAUNCH_CHECK("k_gg_reduce");
+        }
+        if (n == 0) {
+            // the loss partials of mode 0 are consumed before the last mode reuses the buffer
+            k_loss<AT><<<1, 1024, 0, s>>>(w.part, nblk0, 0.5 * scale, loss);
+            TK_LAUNCH_CHECK("k_loss");
+        }
+    }
+    return TK_OK;
+}
+
+}  // namespace
+
+void free_completion_ws(tk_ctx* ctx) {
+    CompletionWs& w = ctx->cws;
+    void* ps[] = {w.e, w.W, w.Gn, w.part};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    for (int n = 0; n < kMaxOrder; ++n)
+        if (w.rowid[n]) (void)hipFree(w.rowid[n]);
+    w = CompletionWs{};
+}
+
+int adjoint_run(tk_ctx* ctx, const void* G, const void* const* U, void* loss, void* gG, void* const* gU,
+                hipStream_t s) {
+    if (ctx->dtype == TK_F64)
+        return adjoint_typed<double>(ctx, (const double*)G, (const double* const*)U, (double*)loss, (double*)gG,
+                                     (double* const*)gU, s);
+    return adjoint_typed<float>(ctx, (const float*)G, (const float* const*)U, (float*)loss, (float*)gG,
+                                (float* const*)gU, s);
+}
+
+}  // namespace tk

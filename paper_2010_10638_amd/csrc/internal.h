@@ -96,6 +96,16 @@ struct Workspace {
     double* scal = nullptr;         // small device scalars (fit when the caller gives none)
 };
 
+// Completion (adjoint TTMc) workspace, allocated on the first ttmc_adjoint call
+struct CompletionWs {
+    bool ready = false;
+    int32_t* rowid[kMaxOrder] = {};  // per mode: compressed row of every padded position
+    void* e = nullptr;               // residuals on one mode's padded stream (parameter type)
+    void* W = nullptr;               // U_n G_(n), max_n I_n x K_n
+    void* Gn = nullptr;              // mode-n unfolding of the core
+    double* part = nullptr;          // loss and core-gradient partials
+};
+
 }  // namespace tk
 
 struct tk_ctx {
@@ -110,10 +120,11 @@ struct tk_ctx {
     void* Ulp[tk::kMaxOrder] = {};   // factor copies in TTMc precision, I_k x ldU[k]
     int ldU[tk::kMaxOrder] = {};
     tk::Workspace ws;
+    tk::CompletionWs cws;
     hipStream_t last_stream = nullptr;
     int device = 0;
     // region timing of hooi_sweep (tucker_profile)
-    hipEvent_t* prof_ev = nullptr;   // [capacity][2N + 2]
+    hipEvent_t* prof_ev = nullptr;   // [capacity][4N + 2]
     int prof_cap = 0;
     int prof_used = 0;
 };
@@ -170,8 +181,15 @@ int convert_factor(tk_ctx* ctx, int k, const double* U, hipStream_t s);
 int fill_zero(void* p, size_t bytes, hipStream_t s);
 
 // TTMc (ttmc.hip): uses ctx->Ulp copies
-// ev_main (optional, [2]): events recorded on s around the main TTMc kernel (fix-up excluded)
-int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main = nullptr);
+// ev_main (optional, [2]): events recorded on s around the main TTMc kernel (fix-up excluded);
+// val (optional): values on the mode's padded stream to use instead of the tensor's (same type)
+int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main = nullptr,
+             const void* val = nullptr);
+// Completion (completion.hip): loss and gradients over the context's entries, parameters in the
+// context's TTMc type (FP32 or FP64)
+int adjoint_run(tk_ctx* ctx, const void* G, const void* const* U, void* loss, void* gG, void* const* gU,
+                hipStream_t s);
+void free_completion_ws(tk_ctx* ctx);
 
 // QRP (qrp.hip): Y -> U (FP64) and the low-precision copy ctx->Ulp[mode]
 int qrp_run(tk_ctx* ctx, int mode, const void* Y, double* U, int32_t* piv, hipStream_t s);

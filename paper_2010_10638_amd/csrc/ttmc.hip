@@ -438,6 +438,163 @@ __global__ __launch_bounds__(256) void k_ttmc_generic(TtmcArgs a) {
     }
 }
 
+// Order >= 4, fiber-factored (the Kronecker row of a nonzero is (kron of its inner modes' rows)
+// kron U_f(i_f, :), f the last other mode).  Within a row the nonzeros are sorted by i_f, so the
+// nonzeros sharing i_f form a fiber, and
+//     Y_(n)(i_n, :) = sum_fibers  s_fiber kron U_f(i_f, :),   s_fiber = sum_p x_p kron_inner(p),
+// which needs Ks = prod_inner R products per nonzero and Ks * R_f per fiber instead of K_n per
+// nonzero.  Lane l owns the inner columns cs = l + 64 j (j < KSL) and keeps s and the row
+// accumulator Y[cs][0..R_f) in registers.  Per batch of 64 nonzeros the wave stages the inner
+// factor rows and the fiber rows in its LDS slot (one nonzero per lane, 16-byte loads) and then
+// walks the batch: a nonzero that starts a fiber first folds the finished fiber into the row
+// (R_f FMAs per column) and loads the new fiber row; a nonzero that starts a row writes the
+// finished row.  Summation order is fixed, so the result is deterministic.
+struct FiberArgs {
+    int32_t nin;                   // inner modes (other modes but the fiber mode)
+    int32_t off[kMaxOrder - 2];    // offset of inner mode k's row in a staged tile row
+    int32_t Rin[kMaxOrder - 2];
+    int32_t Rf;
+    int32_t Ks;                    // prod_inner R
+};
+
+constexpr int kFiberTile = 32;     // staged inner-row values per nonzero (sum of inner ranks)
+
+template <typename AT, typename ST, int KSL, int RF>
+__global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
+    struct Slot {
+        AT in[64][kFiberTile + 1];
+        AT uf[64][RF + 1];
+        AT x[64];
+    };
+    __shared__ Slot slots[4];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ch = blockIdx.x * 4 + w;
+    if (ch >= a.nchunks) return;
+    Slot& T = slots[w];
+    const int nm1 = a.nm1, fs = nm1 - 1;   // the fiber mode is the last other mode
+    const int q0 = a.chunk_ptr[ch], q1 = a.chunk_ptr[ch + 1];
+    const int slot = a.chunk_slot[ch];
+    const int s0 = a.chunk_row[ch];
+    const int K = a.K, Rf = f.Rf;
+    // tile offsets of this lane's inner columns (loops unrolled: the arrays stay in registers)
+    int toff[KSL][kMaxOrder - 2];
+#pragma unroll
+    for (int j = 0; j < KSL; ++j) {
+        int rem = lane + 64 * j;
+#pragma unroll
+        for (int k = kMaxOrder - 3; k >= 0; --k) {
+            toff[j][k] = 0;
+            if (k < f.nin) {
+                toff[j][k] = f.off[k] + rem % f.Rin[k];
+                rem /= f.Rin[k];
+            }
+        }
+    }
+    AT sacc[KSL], yacc[KSL][RF], u[RF];
+#pragma unroll
+    for (int j = 0; j < KSL; ++j) {
+        sacc[j] = AT(0);
+#pragma unroll
+        for (int r = 0; r < RF; ++r) yacc[j][r] = AT(0);
+    }
+#pragma unroll
+    for (int r = 0; r < RF; ++r) u[r] = AT(0);
+    int srow = s0;
+    int prev_if = -1;
+    auto fold = [&]() {
+#pragma unroll
+        for (int j = 0; j < KSL; ++j) {
+#pragma unroll
+            for (int r = 0; r < RF; ++r) yacc[j][r] += sacc[j] * u[r];
+            sacc[j] = AT(0);
+        }
+    };
+    auto flush_row = [&]() {
+        const bool owner = (srow != s0) || (slot < 0);
+        AT* dst = owner ? (AT*)a.Y + (int64_t)ld_const(a.rows, srow) * K : (AT*)a.carry + (int64_t)slot * K;
+#pragma unroll
+        for (int j = 0; j < KSL; ++j) {
+            const int cs = lane + 64 * j;
+            if (cs < f.Ks) {
+#pragma unroll
+                for (int r = 0; r < RF; ++r)
+                    if (r < Rf) dst[(int64_t)cs * Rf + r] = yacc[j][r];
+            }
+#pragma unroll
+            for (int r = 0; r < RF; ++r) yacc[j][r] = AT(0);
+        }
+        if (owner) zero_gaps<AT>(a, srow, lane);
+    };
+    for (int p = q0; p < q1; p += 64) {
+        const int n = min(64, q1 - p);
+        // stage: one nonzero per lane
+        const int qq = p + lane;
+        const bool valid = lane < n;
+        int iflag = 0, ifib = 0;
+        if (valid) {
+            const int32_t i0 = a.idx[qq];
+            iflag = (i0 < 0) ? 1 : 0;
+            T.x[lane] = load_as<AT, ST>(a.val, (int64_t)qq);
+            for (int t = 0; t < nm1; ++t) {
+                const int32_t it = (t == 0) ? (i0 & kIndexMask) : a.idx[(int64_t)t * a.nnz + qq];
+                // the whole padded row (16 columns, 16-byte loads), then the first R values
+                const uint4* row = (const uint4*)((const ST*)a.F[t] + (int64_t)it * a.ld[t]);
+                constexpr int NV = 16 * (int)sizeof(ST) / 16;
+                uint4 raw[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) raw[v] = row[v];
+                const ST* vals = (const ST*)raw;
+                if (t == fs) {
+                    ifib = it;
+#pragma unroll
+                    for (int r = 0; r < RF; ++r) T.uf[lane][r] = (r < Rf) ? load_as<AT, ST>(vals, (int64_t)r) : AT(0);
+                } else {
+                    const int R = f.Rin[t], o = f.off[t];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        if (r < R) T.in[lane][o + r] = load_as<AT, ST>(vals, (int64_t)r);
+                }
+            }
+        }
+        // fiber starts: a row start, or i_f differs from the previous nonzero's
+        int prev = __shfl_up(ifib, 1);
+        if (lane == 0) prev = prev_if;
+        const uint64_t rstart = __ballot(valid && iflag);
+        const uint64_t fstart = __ballot(valid && (iflag || ifib != prev));
+        prev_if = __shfl(ifib, n - 1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int t = 0; t < n; ++t) {
+            const bool first = (p + t == q0);
+            if (((fstart >> t) & 1ull) || first) {
+                if (!first) fold();
+                if (((rstart >> t) & 1ull) && !first) {
+                    flush_row();
+                    ++srow;
+                }
+#pragma unroll
+                for (int r = 0; r < RF; ++r) u[r] = T.uf[t][r];
+            }
+            const AT x = T.x[t];
+#pragma unroll
+            for (int j = 0; j < KSL; ++j) {
+                AT v = x;
+#pragma unroll
+                for (int k = 0; k < kMaxOrder - 2; ++k)
+                    if (k < f.nin) v *= T.in[t][toff[j][k]];
+                sacc[j] += v;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    fold();
+    flush_row();
+}
+
 // Adds the carry slots of each split row, in slot order, to the row written by its owner.
 template <typename AT>
 __global__ __launch_bounds__(256) void k_ttmc_fixup(const int32_t* __restrict__ split,
@@ -472,9 +629,37 @@ int launch_generic(const TtmcArgs& a, hipStream_t s) {
 #undef TK_GEN
 }
 
+template <typename AT, typename ST>
+int launch_fiber_typed(const TtmcArgs& a, const FiberArgs& f, hipStream_t s) {
+    const unsigned grid = (unsigned)((a.nchunks + 3) / 4);
+    const int ksl = (f.Ks + 63) / 64;
+#define TK_FIB(KSL, RF)                                                      \
+    {                                                                        \
+        k_ttmc_fiber<AT, ST, KSL, RF><<<grid, 256, 0, s>>>(a, f);            \
+        TK_LAUNCH_CHECK("k_ttmc_fiber");                                     \
+        return TK_OK;                                                        \
+    }
+    if (f.Rf <= 8) {
+        if (ksl <= 1) TK_FIB(1, 8)
+        if (ksl <= 2) TK_FIB(2, 8)
+        if (ksl <= 4) TK_FIB(4, 8)
+        TK_FIB(8, 8)
+    }
+    if (ksl <= 1) TK_FIB(1, 16)
+    if (ksl <= 2) TK_FIB(2, 16)
+    TK_FIB(4, 16)
+#undef TK_FIB
+}
+
+int launch_fiber(int dtype, const TtmcArgs& a, const FiberArgs& f, hipStream_t s) {
+    if (dtype == TK_F64) return launch_fiber_typed<double, double>(a, f, s);
+    if (dtype == TK_F32) return launch_fiber_typed<float, float>(a, f, s);
+    return launch_fiber_typed<float, bf16_t>(a, f, s);
+}
+
 }  // namespace
 
-int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main) {
+int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main, const void* val) {
     const ModeLayout& ml = ctx->mode[mode];
     const int N = ctx->N;
     const int64_t In = ctx->dims[mode];
@@ -496,7 +681,7 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main)
     a.In = (int32_t)In;
     a.idx = ml.idx;
     a.nnz = ml.P;
-    a.val = ml.val;
+    a.val = val ? val : ml.val;
     a.nm1 = N - 1;
     a.K = (int32_t)ml.K;
     a.Y = Y;
@@ -511,6 +696,25 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main)
     }
     const unsigned grid = (unsigned)((ml.nchunks + 3) / 4);
     int st = TK_OK;
+    // fiber-factored kernel for order >= 4 (fiber mode = last other mode)
+    FiberArgs fa{};
+    bool fiber_ok = N >= 4 && ml.fiber_slot == N - 2;
+    if (fiber_ok) {
+        fa.nin = N - 2;
+        int off = 0;
+        fa.Ks = 1;
+        bool small = true;   // every staged row fits the 16 loaded columns
+        for (int k = 0; k < N - 2; ++k) {
+            small = small && a.R[k] <= 16;
+            fa.off[k] = off;
+            fa.Rin[k] = a.R[k];
+            off += a.R[k];
+            fa.Ks *= a.R[k];
+        }
+        fa.Rf = a.R[N - 2];
+        fiber_ok = small && off <= kFiberTile &&
+                   ((fa.Rf <= 8 && fa.Ks <= 64 * 8) || (fa.Rf <= 16 && fa.Ks <= 64 * 4));
+    }
     if (ev_main) TK_HIP(hipEventRecord(ev_main[0], s));
     if (mfma_ok) {
         if (ctx->dtype == TK_F64) {
@@ -523,6 +727,9 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main)
             k_ttmc3_lds<bf16_t><<<grid, 256, 0, s>>>(a);
             TK_LAUNCH_CHECK("k_ttmc3_lds");
         }
+    } else if (fiber_ok) {
+        st = launch_fiber(ctx->dtype, a, fa, s);
+        if (st) return st;
     } else {
         if (ctx->dtype == TK_F64) st = launch_generic<double, double>(a, s);
         else if (ctx->dtype == TK_F32) st = launch_generic<float, float>(a, s);

@@ -116,8 +116,11 @@ TTMC_CASES = [
     ([40, 300, 200], [16, 16, 16], 20000),     # order-3 MFMA path, long rows (split)
     ([500, 80, 60], [10, 10, 10], 12000),      # R = 10 (padded tile), empty rows in mode 0
     ([64, 48, 32], [8, 8, 8], 3000),
-    ([30, 20, 25, 12], [3, 4, 2, 3], 5000),    # order 4, generic path
-    ([12, 10, 9, 8, 7], [2, 3, 2, 2, 2], 2500),  # order 5
+    ([30, 20, 25, 12], [3, 4, 2, 3], 5000),    # order 4, fiber-factored (short fibers)
+    ([12, 10, 9, 8, 7], [2, 3, 2, 2, 2], 2500),  # order 5, fiber-factored (3 inner modes)
+    ([400, 300, 60, 9], [8, 8, 8, 8], 30000),  # order 4, K = 512: 64 inner columns, R_f = 8, long fibers
+    ([50, 40, 30, 20], [4, 12, 12, 16], 20000),  # order 4: 144-192 inner columns, R_f = 16 or 12
+    ([20, 18, 16, 14], [20, 3, 4, 5], 8000),   # inner rank > 16 for some modes: generic path
     ([300, 250], [6, 6], 4000),                # order 2 (SpMM); R_1 <= K_1 = R_2 forces equal ranks
     ([50, 40, 30], [20, 3, 17], 4000),         # R > 16: generic path for order 3
 ]
