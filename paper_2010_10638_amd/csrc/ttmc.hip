@@ -444,51 +444,59 @@ __global__ __launch_bounds__(256) void k_ttmc_generic(TtmcArgs a) {
 //     Y_(n)(i_n, :) = sum_fibers  s_fiber kron U_f(i_f, :),   s_fiber = sum_p x_p kron_inner(p),
 // which needs Ks = prod_inner R products per nonzero and Ks * R_f per fiber instead of K_n per
 // nonzero.  Lane l owns the inner columns cs = l + 64 j (j < KSL) and keeps s and the row
-// accumulator Y[cs][0..R_f) in registers.  Per batch of 64 nonzeros the wave stages the inner
-// factor rows and the fiber rows in its LDS slot (one nonzero per lane, 16-byte loads) and then
-// walks the batch: a nonzero that starts a fiber first folds the finished fiber into the row
-// (R_f FMAs per column) and loads the new fiber row; a nonzero that starts a row writes the
-// finished row.  Summation order is fixed, so the result is deterministic.
+// accumulator Y[cs][0..R_f) in registers.
+// Per batch of 64 nonzeros (one per lane) the wave stages the inner factor rows transposed
+// (column-major: value c of nonzero e at c * kFiberStride + e) and the fiber rows in its LDS slot;
+// the index loads run two batches ahead and the 16-byte row loads one batch ahead, so both are in
+// flight while the previous batch is walked.  The walk takes four nonzeros at a time: one 16-byte
+// LDS read per inner mode gives a lane its factor values of all four.  A nonzero that starts a
+// fiber first folds the finished fiber into the row (R_f FMAs per column) and loads the new fiber
+// row; a nonzero that starts a row writes the finished row.  Summation order is fixed: the result
+// is deterministic.
 struct FiberArgs {
     int32_t nin;                   // inner modes (other modes but the fiber mode)
     int32_t off[kMaxOrder - 2];    // offset of inner mode k's row in a staged tile row
     int32_t Rin[kMaxOrder - 2];
     int32_t Rf;
     int32_t Ks;                    // prod_inner R
+    int32_t tw;                    // staged values per nonzero: sum_inner R (<= kFiberTile)
 };
 
-constexpr int kFiberTile = 32;     // staged inner-row values per nonzero (sum of inner ranks)
+constexpr int kFiberTile = 32;
 
-template <typename AT, typename ST, int KSL, int RF>
+constexpr int kFiberStride = 68;   // transposed tile row: 64 nonzeros + 4 (16-byte aligned rows)
+
+template <typename AT, int RF>
+__host__ __device__ constexpr int fiber_slot_words(int tw) {
+    // in[tw][kFiberStride] (transposed), uf[64][RF], x[64]  (in units of AT)
+    return tw * kFiberStride + 64 * RF + 64;
+}
+
+template <typename AT, typename ST, int NM1, int KSL, int RF>
 __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
-    struct Slot {
-        AT in[64][kFiberTile + 1];
-        AT uf[64][RF + 1];
-        AT x[64];
-    };
-    __shared__ Slot slots[4];
+    extern __shared__ __align__(16) unsigned char fiber_lds[];
+    constexpr int NV = 16 * (int)sizeof(ST) / 16;   // 16-byte loads per padded (16-column) row
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ch = blockIdx.x * 4 + w;
     if (ch >= a.nchunks) return;
-    Slot& T = slots[w];
-    const int nm1 = a.nm1, fs = nm1 - 1;   // the fiber mode is the last other mode
+    typedef AT at4 __attribute__((ext_vector_type(4)));
+    AT* Tin = (AT*)fiber_lds + (size_t)w * fiber_slot_words<AT, RF>(f.tw);
+    AT* Tuf = Tin + f.tw * kFiberStride;
+    AT* Tx = Tuf + 64 * RF;
     const int q0 = a.chunk_ptr[ch], q1 = a.chunk_ptr[ch + 1];
     const int slot = a.chunk_slot[ch];
     const int s0 = a.chunk_row[ch];
     const int K = a.K, Rf = f.Rf;
     // tile offsets of this lane's inner columns (loops unrolled: the arrays stay in registers)
-    int toff[KSL][kMaxOrder - 2];
+    int toff[KSL][NM1 - 1];
 #pragma unroll
     for (int j = 0; j < KSL; ++j) {
         int rem = lane + 64 * j;
 #pragma unroll
-        for (int k = kMaxOrder - 3; k >= 0; --k) {
-            toff[j][k] = 0;
-            if (k < f.nin) {
-                toff[j][k] = f.off[k] + rem % f.Rin[k];
-                rem /= f.Rin[k];
-            }
+        for (int k = NM1 - 2; k >= 0; --k) {
+            toff[j][k] = f.off[k] + rem % f.Rin[k];
+            rem /= f.Rin[k];
         }
     }
     AT sacc[KSL], yacc[KSL][RF], u[RF];
@@ -502,6 +510,31 @@ __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
     for (int r = 0; r < RF; ++r) u[r] = AT(0);
     int srow = s0;
     int prev_if = -1;
+
+    // prefetch registers: indices and value of the next-but-one batch, rows of the next batch
+    // (indices in a 4-vector, NM1 <= 4, so they stay in registers)
+    typedef int32_t i4v __attribute__((ext_vector_type(4)));
+    static_assert(NM1 <= 4, "fiber kernel: order <= 5");
+    i4v i1 = {0, 0, 0, 0}, i2 = {0, 0, 0, 0};
+    AT x1 = AT(0), x2 = AT(0);
+    uint4 raw[NM1][NV];
+    auto load_idx = [&](int p, i4v& ix, AT& xv) {
+        const int qq = p + lane;
+        const bool v = qq < q1;
+        const int qc = v ? qq : q1 - 1;
+#pragma unroll
+        for (int t = 0; t < NM1; ++t) ix[t] = a.idx[(int64_t)t * a.nnz + qc];
+        xv = load_as<AT, ST>(a.val, (int64_t)qc);
+    };
+    auto load_rows = [&](const i4v ix) {
+#pragma unroll
+        for (int t = 0; t < NM1; ++t) {
+            const int32_t it = (t == 0) ? (ix[0] & kIndexMask) : ix[t];
+            const uint4* row = (const uint4*)((const ST*)a.F[t] + (int64_t)it * a.ld[t]);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) raw[t][v] = row[v];
+        }
+    };
     auto fold = [&]() {
 #pragma unroll
         for (int j = 0; j < KSL; ++j) {
@@ -512,7 +545,10 @@ __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
     };
     auto flush_row = [&]() {
         const bool owner = (srow != s0) || (slot < 0);
-        AT* dst = owner ? (AT*)a.Y + (int64_t)ld_const(a.rows, srow) * K : (AT*)a.carry + (int64_t)slot * K;
+        // select the base as an integer (a pointer select here was lowered through scratch)
+        const uint64_t base = owner ? (uint64_t)(uintptr_t)a.Y : (uint64_t)(uintptr_t)a.carry;
+        const int64_t row0 = owner ? (int64_t)ld_const(a.rows, srow) * K : (int64_t)slot * K;
+        AT* dst = (AT*)(uintptr_t)base + row0;
 #pragma unroll
         for (int j = 0; j < KSL; ++j) {
             const int cs = lane + 64 * j;
@@ -526,65 +562,79 @@ __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
         }
         if (owner) zero_gaps<AT>(a, srow, lane);
     };
+
+    load_idx(q0, i1, x1);
+    if (q0 + 64 < q1) load_idx(q0 + 64, i2, x2);
+    load_rows(i1);
     for (int p = q0; p < q1; p += 64) {
         const int n = min(64, q1 - p);
-        // stage: one nonzero per lane
-        const int qq = p + lane;
         const bool valid = lane < n;
-        int iflag = 0, ifib = 0;
-        if (valid) {
-            const int32_t i0 = a.idx[qq];
-            iflag = (i0 < 0) ? 1 : 0;
-            T.x[lane] = load_as<AT, ST>(a.val, (int64_t)qq);
-            for (int t = 0; t < nm1; ++t) {
-                const int32_t it = (t == 0) ? (i0 & kIndexMask) : a.idx[(int64_t)t * a.nnz + qq];
-                // the whole padded row (16 columns, 16-byte loads), then the first R values
-                const uint4* row = (const uint4*)((const ST*)a.F[t] + (int64_t)it * a.ld[t]);
-                constexpr int NV = 16 * (int)sizeof(ST) / 16;
-                uint4 raw[NV];
+        // stage this batch: its rows (loaded one batch ago) into the LDS slot
+        const int iflag = (valid && i1[0] < 0) ? 1 : 0;
+        const int ifib = i1[NM1 - 1];
+        Tx[lane] = valid ? x1 : AT(0);
+        {
+            int kin = 0;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) raw[v] = row[v];
-                const ST* vals = (const ST*)raw;
-                if (t == fs) {
-                    ifib = it;
+            for (int t = 0; t < NM1; ++t) {
+                const ST* vals = (const ST*)raw[t];
+                if (t == NM1 - 1) {
 #pragma unroll
-                    for (int r = 0; r < RF; ++r) T.uf[lane][r] = (r < Rf) ? load_as<AT, ST>(vals, (int64_t)r) : AT(0);
+                    for (int r = 0; r < RF; ++r) Tuf[lane * RF + r] = (r < Rf) ? load_as<AT, ST>(vals, (int64_t)r) : AT(0);
                 } else {
-                    const int R = f.Rin[t], o = f.off[t];
+                    const int R = f.Rin[kin], o = f.off[kin];
 #pragma unroll
                     for (int r = 0; r < 16; ++r)
-                        if (r < R) T.in[lane][o + r] = load_as<AT, ST>(vals, (int64_t)r);
+                        if (r < R) Tin[(o + r) * kFiberStride + lane] = load_as<AT, ST>(vals, (int64_t)r);
+                    ++kin;
                 }
             }
         }
-        // fiber starts: a row start, or i_f differs from the previous nonzero's
+        // fiber and row starts of this batch
         int prev = __shfl_up(ifib, 1);
         if (lane == 0) prev = prev_if;
-        const uint64_t rstart = __ballot(valid && iflag);
+        const uint64_t rstart = __ballot(iflag);
         const uint64_t fstart = __ballot(valid && (iflag || ifib != prev));
         prev_if = __shfl(ifib, n - 1);
+        // prefetch: rows of the next batch, indices of the one after
+        if (p + 64 < q1) {
+            i1 = i2;
+            x1 = x2;
+            load_rows(i1);
+            if (p + 128 < q1) load_idx(p + 128, i2, x2);
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int t = 0; t < n; ++t) {
-            const bool first = (p + t == q0);
-            if (((fstart >> t) & 1ull) || first) {
-                if (!first) fold();
-                if (((rstart >> t) & 1ull) && !first) {
-                    flush_row();
-                    ++srow;
-                }
-#pragma unroll
-                for (int r = 0; r < RF; ++r) u[r] = T.uf[t][r];
-            }
-            const AT x = T.x[t];
+        // walk the batch, four nonzeros at a time (n is a multiple of 4)
+        for (int t0 = 0; t0 < n; t0 += 4) {
+            const at4 xv = *(const at4*)&Tx[t0];
+            at4 pr[KSL];
 #pragma unroll
             for (int j = 0; j < KSL; ++j) {
-                AT v = x;
+                at4 v = xv;
 #pragma unroll
-                for (int k = 0; k < kMaxOrder - 2; ++k)
-                    if (k < f.nin) v *= T.in[t][toff[j][k]];
-                sacc[j] += v;
+                for (int k = 0; k < NM1 - 1; ++k) v *= *(const at4*)&Tin[toff[j][k] * kFiberStride + t0];
+                pr[j] = v;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int t = t0 + e;
+                const bool first = (p + t == q0);
+                if (((fstart >> t) & 1ull) || first) {
+                    if (!first) fold();
+                    if (((rstart >> t) & 1ull) && !first) {
+                        flush_row();
+                        ++srow;
+                    }
+#pragma unroll
+                    for (int r = 0; r < RF; r += 4) {
+                        const at4 uv = *(const at4*)&Tuf[t * RF + r];
+                        u[r] = uv.x; u[r + 1] = uv.y; u[r + 2] = uv.z; u[r + 3] = uv.w;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < KSL; ++j) sacc[j] += pr[j][e];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -629,15 +679,16 @@ int launch_generic(const TtmcArgs& a, hipStream_t s) {
 #undef TK_GEN
 }
 
-template <typename AT, typename ST>
+template <typename AT, typename ST, int NM1>
 int launch_fiber_typed(const TtmcArgs& a, const FiberArgs& f, hipStream_t s) {
     const unsigned grid = (unsigned)((a.nchunks + 3) / 4);
     const int ksl = (f.Ks + 63) / 64;
-#define TK_FIB(KSL, RF)                                                      \
-    {                                                                        \
-        k_ttmc_fiber<AT, ST, KSL, RF><<<grid, 256, 0, s>>>(a, f);            \
-        TK_LAUNCH_CHECK("k_ttmc_fiber");                                     \
-        return TK_OK;                                                        \
+#define TK_FIB(KSL, RF)                                                                        \
+    {                                                                                          \
+        const size_t lds = (size_t)4 * fiber_slot_words<AT, RF>(f.tw) * sizeof(AT);            \
+        k_ttmc_fiber<AT, ST, NM1, KSL, RF><<<grid, 256, lds, s>>>(a, f);                       \
+        TK_LAUNCH_CHECK("k_ttmc_fiber");                                                       \
+        return TK_OK;                                                                          \
     }
     if (f.Rf <= 8) {
         if (ksl <= 1) TK_FIB(1, 8)
@@ -651,10 +702,16 @@ int launch_fiber_typed(const TtmcArgs& a, const FiberArgs& f, hipStream_t s) {
 #undef TK_FIB
 }
 
+template <int NM1>
+int launch_fiber_n(int dtype, const TtmcArgs& a, const FiberArgs& f, hipStream_t s) {
+    if (dtype == TK_F64) return launch_fiber_typed<double, double, NM1>(a, f, s);
+    if (dtype == TK_F32) return launch_fiber_typed<float, float, NM1>(a, f, s);
+    return launch_fiber_typed<float, bf16_t, NM1>(a, f, s);
+}
+
 int launch_fiber(int dtype, const TtmcArgs& a, const FiberArgs& f, hipStream_t s) {
-    if (dtype == TK_F64) return launch_fiber_typed<double, double>(a, f, s);
-    if (dtype == TK_F32) return launch_fiber_typed<float, float>(a, f, s);
-    return launch_fiber_typed<float, bf16_t>(a, f, s);
+    if (a.nm1 == 3) return launch_fiber_n<3>(dtype, a, f, s);
+    return launch_fiber_n<4>(dtype, a, f, s);
 }
 
 }  // namespace
@@ -712,7 +769,8 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
             fa.Ks *= a.R[k];
         }
         fa.Rf = a.R[N - 2];
-        fiber_ok = small && off <= kFiberTile &&
+        fa.tw = off;
+        fiber_ok = small && (N == 4 || N == 5) && off <= kFiberTile &&
                    ((fa.Rf <= 8 && fa.Ks <= 64 * 8) || (fa.Rf <= 16 && fa.Ks <= 64 * 4));
     }
     if (ev_main) TK_HIP(hipEventRecord(ev_main[0], s));
