@@ -12,6 +12,8 @@
 // values in the ordinary TTMc kernels (the adjoint reuses the forward kernels unchanged), and two
 // small dense products give the gradients.  All sums have a fixed order: results are
 // deterministic.
+#include <type_traits>
+
 #include "internal.h"
 #include "atb.h"
 
@@ -150,6 +152,84 @@ __global__ __launch_bounds__(256) void k_residual(ResidArgs a) {
     }
 }
 
+// Order 3 with R_a, R_b <= 16: the same residuals with the factor rows read by 16-byte loads and
+// the W rows of the (few) compressed rows a workgroup's 256 positions touch staged in LDS; the
+// model value of an entry is a^T M b with M = W(i_n, :) as an R_a x R_b matrix (K FMAs).  A
+// workgroup spanning more than kResidRows rows reads M from global memory instead.
+constexpr int kResidRows = 8;
+
+template <typename AT>
+__global__ __launch_bounds__(256) void k_residual3(ResidArgs a) {
+    extern __shared__ __align__(16) unsigned char resid_lds[];
+    AT* Ms = (AT*)resid_lds;                       // [kResidRows][K]
+    __shared__ double red[4];
+    const int64_t P = a.P;
+    const int64_t b0 = (int64_t)blockIdx.x * 256;
+    const int64_t q = b0 + threadIdx.x;
+    const int64_t bl = min(P, b0 + 256) - 1;
+    const int s_first = a.rowid[b0], s_last = a.rowid[bl];
+    const int nr = s_last - s_first + 1;
+    const int K = (int)a.K, Ra = a.R[0], Rb = a.R[1];
+    const bool staged = nr <= kResidRows;
+    if (staged) {
+        for (int e = threadIdx.x; e < nr * K; e += 256) {
+            const int r = e / K, c = e % K;
+            Ms[e] = ((const AT*)a.W)[(int64_t)a.rows[s_first + r] * K + c];
+        }
+    }
+    __syncthreads();
+    double e2 = 0.0;
+    if (q < P) {
+        const int s = a.rowid[q];
+        const bool real = (q - a.pptr[s]) < (int64_t)(a.ptr[s + 1] - a.ptr[s]);
+        const int32_t ia = a.idx[q] & kIndexMask;
+        const int32_t ib = a.idx[P + q];
+        // factor rows: the whole padded row (16 columns), 16-byte loads
+        constexpr int NV = 16 * (int)sizeof(AT) / 16;
+        uint4 ra[NV], rb[NV];
+        const uint4* pa = (const uint4*)((const AT*)a.F[0] + (int64_t)ia * a.ld[0]);
+        const uint4* pb = (const uint4*)((const AT*)a.F[1] + (int64_t)ib * a.ld[1]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { ra[v] = pa[v]; rb[v] = pb[v]; }
+        const AT* av = (const AT*)ra;
+        const AT* bv = (const AT*)rb;
+        // a^T M b; instantiated per address space of M (LDS or global memory) and for R_b = 16
+        // (row stride known: vector reads of M)
+        auto model = [&](const AT* M, auto rb_const) {
+            constexpr int RBC = decltype(rb_const)::value;
+            const int ld = RBC ? RBC : Rb;
+            AT xh = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if (i < Ra) {
+                    AT t = 0;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j)
+                        if (RBC || j < Rb) t += M[i * ld + j] * bv[j];
+                    xh += av[i] * t;
+                }
+            }
+            return xh;
+        };
+        using RB16 = std::integral_constant<int, 16>;
+        using RBN = std::integral_constant<int, 0>;
+        const AT* Ml = Ms + (int64_t)(s - s_first) * K;
+        const AT* Mg = (const AT*)a.W + (int64_t)a.rows[s] * K;
+        AT xh;
+        if (Rb == 16) xh = staged ? model(Ml, RB16{}) : model(Mg, RB16{});
+        else xh = staged ? model(Ml, RBN{}) : model(Mg, RBN{});
+        const AT ev = real ? xh - ((const AT*)a.val)[q] : AT(0);
+        ((AT*)a.e)[q] = ev;
+        e2 = (double)ev * (double)ev;
+    }
+    if (a.part) {
+        for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
+        __syncthreads();
+        if (threadIdx.x == 0) a.part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    }
+}
+
 // gU[i][r] = scale * sum_c Y[i][c] Gn[r][c]   (c ascending, FP64 accumulation)
 template <typename AT>
 __global__ void k_gu(const AT* __restrict__ Y, const AT* __restrict__ Gn, int64_t I, int R, int64_t K,
@@ -161,6 +241,36 @@ __global__ void k_gu(const AT* __restrict__ Y, const AT* __restrict__ Gn, int64_
     double acc = 0.0;
     for (int64_t c = 0; c < K; ++c) acc += (double)Y[i * K + c] * (double)Gn[(int64_t)r * K + c];
     gU[e] = (AT)(scale * acc);
+}
+
+// Same product, R <= 16: one thread per row i holds its R sums (FP64) and walks the row of Y with
+// 16-byte loads; Gn sits in LDS (read by all lanes at the same address).
+template <typename AT>
+__global__ __launch_bounds__(256) void k_gu_rows(const AT* __restrict__ Y, const AT* __restrict__ Gn, int64_t I,
+                                                 int R, int K, double scale, AT* __restrict__ gU) {
+    extern __shared__ __align__(16) unsigned char gu_lds[];
+    AT* G = (AT*)gu_lds;   // [R][K]
+    for (int e = threadIdx.x; e < R * K; e += 256) G[e] = Gn[e];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= I) return;
+    double acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+    const AT* y = Y + i * K;
+    constexpr int V = 16 / (int)sizeof(AT);   // values per 16-byte load
+    for (int c0 = 0; c0 < K; c0 += V) {
+        AT yv[V];
+        *(uint4*)yv = *(const uint4*)(y + c0);
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (r < R) acc[r] += (double)yv[u] * (double)G[r * K + c0 + u];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (r < R) gU[i * R + r] = (AT)(scale * acc[r]);
 }
 
 // part[split][r][c] = sum_{i in slab} U[i][r] Y[i][c] on FP64 MFMA (same blocking as the core)
@@ -337,15 +447,27 @@ int adjoint_typed(tk_ctx* ctx, const AT* G, const AT* const* U, AT* loss, AT* gG
             ra.W = w.W;
             ra.e = w.e;
             ra.part = (n == 0) ? w.part : nullptr;
-            k_residual<AT><<<cdiv(ml.P, 256), 256, 0, s>>>(ra);
-            TK_LAUNCH_CHECK("k_residual");
+            if (N == 3 && ra.R[0] <= 16 && ra.R[1] <= 16 && ctx->ldU[ml.others[0]] == 16 &&
+                ctx->ldU[ml.others[1]] == 16) {
+                const size_t lds = (size_t)kResidRows * K * sizeof(AT);
+                k_residual3<AT><<<cdiv(ml.P, 256), 256, lds, s>>>(ra);
+                TK_LAUNCH_CHECK("k_residual3");
+            } else {
+                k_residual<AT><<<cdiv(ml.P, 256), 256, 0, s>>>(ra);
+                TK_LAUNCH_CHECK("k_residual");
+            }
             if (n == 0) nblk0 = (ml.P + 255) / 256;
         }
         // TTMc_n(E): the forward kernels with the residuals in place of the values
         if ((st = ttmc_run(ctx, n, ctx->ws.y, s, nullptr, w.e))) return st;
         const AT* Y = (const AT*)ctx->ws.y;
-        k_gu<AT><<<cdiv(I * R, 256), 256, 0, s>>>(Y, Gn, I, R, K, scale, gU[n]);
-        TK_LAUNCH_CHECK("k_gu");
+        if (R <= 16 && K % 4 == 0 && (size_t)R * K * sizeof(AT) <= 64 * 1024) {
+            k_gu_rows<AT><<<cdiv(I, 256), 256, (size_t)R * K * sizeof(AT), s>>>(Y, Gn, I, R, (int)K, scale, gU[n]);
+            TK_LAUNCH_CHECK("k_gu_rows");
+        } else {
+            k_gu<AT><<<cdiv(I * R, 256), 256, 0, s>>>(Y, Gn, I, R, K, scale, gU[n]);
+            TK_LAUNCH_CHECK("k_gu");
+        }
         if (n == N - 1) {
             int nsplit;
             int64_t slab;
