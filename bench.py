@@ -148,6 +148,38 @@ def roofline(w, N, flops, bytes_, t_launch, default):
             "traffic": None, **common}
 
 
+def compare_precisions(args, w, tk, torch):
+    """The same sweeps (same initial factors) with each TTMc precision; the FP64 path is the
+    reference for the fit error.  Sweep times are wall-clock per sweep (synchronised), median over
+    the timed sweeps after one warm-up sweep."""
+    import statistics
+    coords = torch.from_numpy(w.coords).cuda()
+    vals = torch.from_numpy(w.vals).cuda()
+    res = {}
+    for dt in ("f64", "f32", "bf16"):
+        ctx = tk.tucker_init(coords, vals, w.dims, w.ranks, dtype=dt)
+        U = [torch.from_numpy(u).cuda() for u in w.U_init]
+        G = torch.empty(w.ranks, dtype=torch.float64, device="cuda")
+        fit = torch.empty(1, dtype=torch.float64, device="cuda")
+        fits, times = [], []
+        for k in range(args.steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tk.hooi_sweep(ctx, U, G, fit)
+            torch.cuda.synchronize()
+            if k > 0:
+                times.append(time.perf_counter() - t0)
+            fits.append(float(fit.item()))
+        res[dt] = {"sweep_ms_median": statistics.median(times) * 1e3, "fits": fits}
+        del ctx
+    ref = res["f64"]["fits"]
+    for dt in ("f32", "bf16"):
+        res[dt]["fit_rel_err_vs_f64"] = max(abs(a - b) / abs(b) for a, b in zip(res[dt]["fits"], ref) if b != 0)
+    out = {"workload": w.name, "dims": w.dims, "ranks": w.ranks, "nnz": int(w.nnz), "sweeps": args.steps + 1,
+           "qrp": "f64", "results": res}
+    print(json.dumps(out), flush=True)
+
+
 def run_completion(args, w, tk, torch):
     """One step = the completion loss and its gradients (adjoint TTMc over every mode) and one
     Adam update of the core and the factors, on the 30M-entry workload."""
@@ -212,6 +244,9 @@ def main():
                     "30M entries, R 16, one Adam step of the completion loss per step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (calibrates FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--compare-precisions", action="store_true",
+                    help="run the workload's HOOI sweeps with FP64, FP32 and BF16 TTMc (FP64 QRP in all) "
+                    "and print per-precision sweep times, fits and the fit error against the FP64 path")
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a markdown summary of a rocprofv3 "
                     "--kernel-trace --stats output directory and exit")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -263,6 +298,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "completion" and not args.small:
         return run_completion(args, w, tk, torch)
+    if args.compare_precisions:
+        return compare_precisions(args, w, tk, torch)
     coords = torch.from_numpy(w.coords).cuda()
     vals = torch.from_numpy(w.vals).cuda()
     ctx = tk.tucker_init(coords, vals, w.dims, w.ranks, dtype=w.dtype)

@@ -329,7 +329,7 @@ int tucker_profile_read(tk_ctx* ctx, double* ttmc_ms, double* ttmc_kernel_ms, do
     double tt[kMaxOrder] = {}, tk_[kMaxOrder] = {}, qq[kMaxOrder] = {}, cc = 0.0;
     for (int k = 0; k < ctx->prof_used; ++k) {
         hipEvent_t* ev = ctx->prof_ev + (size_t)k * per;
-        TK_HIP(hipEventSynchronize(ev[per - 1]));
+        TK_HIP(hipEventSynchronize(ev[2 * N + 1]));   // core end: the last event a sweep records
         float ms = 0.f;
         for (int n = 0; n < N; ++n) {
             TK_HIP(hipEventElapsedTime(&ms, ev[2 * n], ev[2 * n + 1]));

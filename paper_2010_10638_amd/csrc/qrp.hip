@@ -18,8 +18,9 @@
 //   A Cholesky breakdown or a pivot below 1e-12 of the largest diagonal (rank deficiency) sets a
 //   device flag and the Householder kernel below runs instead, on the device, without a host sync.
 //
-// Route 1 (small Y, R_n > 32, K_n > 1024, or the fallback) - eager textbook Householder QRP in
-// one workgroup: exact trailing-norm recompute, first-maximum pivot, v = x + sgn(x_0)||x|| e_1.
+// Route 1 (R_n > 32, K_n > 1024, fat Y without the fat rule, or the fallback) - eager textbook
+// Householder QRP in one workgroup: exact trailing-norm recompute, first-maximum pivot,
+// v = x + sgn(x_0)||x|| e_1.
 // Route 2 (fat Y, K_n > I_n) - the same kernel on Y Y^T (I_n x I_n), as Sec. III-D prescribes.
 #include "internal.h"
 #include "atb.h"
@@ -368,6 +369,29 @@ __device__ inline double block_sum(double v, double* red) {
     return s;
 }
 
+// Column sums  out(c) = sum_{i0 <= i < m} f(i, c)  for c in [c0, n), by one workgroup: lane l of
+// every wave takes column c0 + 64 b + l of column block b (row-major A: coalesced rows), wave w
+// the rows i0 + w, i0 + w + nw, ...; the per-wave partials are added in wave order.
+// emit(c, s, valid) runs on the 64 lanes of wave 0 for every block (valid: c < n).
+template <typename F, typename E>
+__device__ inline void column_sums(int64_t i0, int64_t m, int c0, int n, double* part, F f, E emit) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = (int)(blockDim.x >> 6);
+    for (int cb = c0; cb < n; cb += 64) {
+        const int c = cb + lane;
+        double sacc = 0.0;
+        if (c < n)
+            for (int64_t i = i0 + wv; i < m; i += nw) sacc += f(i, c);
+        part[wv * 64 + lane] = sacc;
+        __syncthreads();
+        if (tid < 64) {
+            double t = 0.0;
+            for (int k = 0; k < nw; ++k) t += part[k * 64 + lane];
+            emit(c, t, c < n);
+        }
+        __syncthreads();
+    }
+}
+
 // Eager Householder QRP on A (m x n, FP64, in place), R steps, by one workgroup (any size up to
 // 1024 threads), then Q[:, :R] = H_0 ... H_{R-1} [I; 0] into U (m x R) and the low-precision copy.
 template <typename YT, typename LT>
@@ -377,8 +401,8 @@ __device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ 
                                double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
                                int32_t* __restrict__ piv_out) {
     __shared__ double red[16];
-    __shared__ double rv[16];
-    __shared__ int rp[16];
+    __shared__ double part[16 * 64];
+    __shared__ double bestv;
     __shared__ int pbest;
     const int tid = threadIdx.x, nt = blockDim.x;
     if (src)
@@ -386,27 +410,24 @@ __device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ 
     for (int c = tid; c < n; c += nt) perm[c] = c;
     __syncthreads();
     for (int j = 0; j < R; ++j) {
-        // trailing norms, exact recompute; first maximum
-        double bv = -1.0;
-        int bp = n;
-        for (int c = j + tid; c < n; c += nt) {
-            double s = 0.0;
-            for (int64_t i = j; i < m; ++i) s += A[i * n + c] * A[i * n + c];
-            if (s > bv) { bv = s; bp = c; }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            double v2 = __shfl_xor(bv, o);
-            int p2 = __shfl_xor(bp, o);
-            if (v2 > bv || (v2 == bv && p2 < bp)) { bv = v2; bp = p2; }
-        }
-        if ((tid & 63) == 0) { rv[tid >> 6] = bv; rp[tid >> 6] = bp; }
+        // trailing norms, exact recompute; first maximum (columns are met in ascending order)
+        if (tid == 0) { bestv = -1.0; pbest = n; }
         __syncthreads();
+        column_sums(j, m, j, n, part, [&](int64_t i, int c) { const double x = A[i * n + c]; return x * x; },
+                    [&](int c, double v, bool valid) {
+                        // lanes of one block in order: wave-level first maximum, then against the best so far
+                        double bv = valid ? v : -1.0;
+                        int bp = valid ? c : n;
+                        for (int o = 1; o < 64; o <<= 1) {
+                            const double v2 = __shfl_xor(bv, o);
+                            const int p2 = __shfl_xor(bp, o);
+                            if (v2 > bv || (v2 == bv && p2 < bp)) { bv = v2; bp = p2; }
+                        }
+                        if ((threadIdx.x & 63) == 0 && bv > bestv) { bestv = bv; pbest = bp; }
+                    });
         if (tid == 0) {
-            double b0 = rv[0];
-            int p0 = rp[0];
-            for (int k = 1; k < nt / 64; ++k)
-                if (rv[k] > b0 || (rv[k] == b0 && rp[k] < p0)) { b0 = rv[k]; p0 = rp[k]; }
-            pbest = p0;
+            if (pbest >= n) pbest = j;   // no comparable norm (NaN): keep the column in place
+            const int p0 = pbest;
             int t = perm[j]; perm[j] = perm[p0]; perm[p0] = t;
         }
         __syncthreads();
@@ -416,9 +437,9 @@ __device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ 
                 double t = A[i * n + j]; A[i * n + j] = A[i * n + p]; A[i * n + p] = t;
             }
         __syncthreads();
-        double part = 0.0;
-        for (int64_t i = j + tid; i < m; i += nt) part += A[i * n + j] * A[i * n + j];
-        const double alpha = sqrt(block_sum(part, red));
+        double part1 = 0.0;
+        for (int64_t i = j + tid; i < m; i += nt) part1 += A[i * n + j] * A[i * n + j];
+        const double alpha = sqrt(block_sum(part1, red));
         if (alpha == 0.0) {
             if (tid == 0) beta_s[j] = 0.0;
             for (int64_t i = tid; i < m; i += nt) V[i * R + j] = 0.0;
@@ -426,7 +447,7 @@ __device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ 
             continue;
         }
         const double x0 = A[(int64_t)j * n + j];
-        part = 0.0;
+        part1 = 0.0;
         for (int64_t i = tid; i < m; i += nt) {
             double v = 0.0;
             if (i >= j) {
@@ -434,18 +455,14 @@ __device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ 
                 if (i == j) v += (x0 >= 0.0 ? 1.0 : -1.0) * alpha;
             }
             V[i * R + j] = v;
-            part += v * v;
+            part1 += v * v;
         }
-        const double vv = block_sum(part, red);
+        const double vv = block_sum(part1, red);
         const double beta = 2.0 / vv;
         if (tid == 0) beta_s[j] = beta;
         __syncthreads();
-        for (int c = j + tid; c < n; c += nt) {
-            double s = 0.0;
-            for (int64_t i = j; i < m; ++i) s += V[i * R + j] * A[i * n + c];
-            w[c] = beta * s;
-        }
-        __syncthreads();
+        column_sums(j, m, j, n, part, [&](int64_t i, int c) { return V[i * R + j] * A[i * n + c]; },
+                    [&](int c, double v, bool valid) { if (valid) w[c] = beta * v; });
         const int64_t cols = n - j;
         for (int64_t e = tid; e < (m - j) * cols; e += nt) {
             const int64_t i = j + e / cols;
@@ -460,12 +477,8 @@ __device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ 
     for (int j = R - 1; j >= 0; --j) {
         const double beta = beta_s[j];
         if (beta == 0.0) continue;
-        for (int c = tid; c < R; c += nt) {
-            double s = 0.0;
-            for (int64_t i = j; i < m; ++i) s += V[i * R + j] * U[i * R + c];
-            w[c] = beta * s;
-        }
-        __syncthreads();
+        column_sums(j, m, 0, R, part, [&](int64_t i, int c) { return V[i * R + j] * U[i * R + c]; },
+                    [&](int c, double v, bool valid) { if (valid) w[c] = beta * v; });
         for (int64_t e = tid; e < (m - j) * R; e += nt) {
             const int64_t i = j + e / R;
             const int c = (int)(e % R);
@@ -493,12 +506,12 @@ __global__ __launch_bounds__(1024) void k_house_qrp(const YT* __restrict__ src, 
     house_qrp_body<YT, LT>(src, A, m, n, R, V, w, beta_s, perm, U, Ulp, ldlp, piv_out);
 }
 
-// U = Y[:, piv] M and its low-precision copy; 16 consecutive threads share a row, one output
+// U = Y[:, piv] M and its low-precision copy; ldlp consecutive threads share a row, one output
 // column each (columns R..ldlp-1 of the copy are zeroed).
 // After a breakdown (device flag set) workgroup 0 runs the Householder QRP on Y instead and the
 // others exit.
 template <typename YT, typename LT>
-__global__ __launch_bounds__(256) void k_form_u(const YT* __restrict__ Y, int64_t m, int n, int R,
+__global__ __launch_bounds__(1024) void k_form_u(const YT* __restrict__ Y, int64_t m, int n, int R,
                                                 const int32_t* __restrict__ pivw,
                                                 const double* __restrict__ M,
                                                 const int32_t* __restrict__ flag,
@@ -512,10 +525,10 @@ __global__ __launch_bounds__(256) void k_form_u(const YT* __restrict__ Y, int64_
     }
     __shared__ double sM[32 * 32];
     __shared__ int sp[32];
-    for (int e = threadIdx.x; e < R * R; e += 256) sM[e] = M[e];
+    for (int e = threadIdx.x; e < R * R; e += blockDim.x) sM[e] = M[e];
     if (threadIdx.x < R) sp[threadIdx.x] = pivw[threadIdx.x];
     __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = g / ldlp;
     const int c = (int)(g % ldlp);
     if (row >= m) return;
@@ -557,7 +570,7 @@ QrpPlan plan(const tk_ctx* ctx, int mode) {
     } else {
         p.m = I;
         p.n = (int)K;
-        p.route = (fat || R > kGramMaxR || K > 1024 || I * K <= 65536) ? 1 : 0;
+        p.route = (fat || R > kGramMaxR || K > 1024) ? 1 : 0;
     }
     int64_t off = 0;
     if (p.route == 0) {
@@ -629,7 +642,7 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
 #undef TK_FINISH
         TK_LAUNCH_CHECK("k_qrp_finish");
         // U = Y[:, piv] M, or (flag set) the Householder fallback on Y in workgroup 0
-        k_form_u<YT, LT><<<cdiv(p.m * ldlp, 256), 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_M, flag, U, Ulp, ldlp,
+        k_form_u<YT, LT><<<cdiv(p.m * ldlp, 1024), 1024, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_M, flag, U, Ulp, ldlp,
                                                              W + p.o_A, W + p.o_V, W + p.o_w, W + p.o_beta, perm, piv);
         TK_LAUNCH_CHECK("k_form_u");
         return TK_OK;

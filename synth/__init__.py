@@ -162,7 +162,9 @@ def skewed(seed: int = 3, dims=(500000, 100000, 365), nnz: int = 50_000_000, R: 
         i3 = rc.integers(0, dims[2], size=b, dtype=np.int64)
         return _ravel([i1, i2, i3], dims)
 
-    keys = _distinct_in_draw_order(draw, nnz, max(1024, nnz // 2))
+    # one batch of 2.6 x nnz draws normally holds nnz distinct coordinates (about 60% of Zipf
+    # draws collide at these sizes); the loop tops up otherwise
+    keys = _distinct_in_draw_order(draw, nnz, max(1024, int(2.6 * nnz)))
     coords = _unravel(keys, dims)
     vals = np.exp(rv.standard_normal(nnz))
     U = [gaussian_qr(ri, d, R) for d in dims]
