@@ -80,6 +80,16 @@ __device__ inline void zero_gaps(const TtmcArgs& a, int s, int lane) {
         for (int64_t e = (int64_t)(g1 + 1) * K + lane; e < (int64_t)a.In * K; e += 64) Y[e] = AT(0);
 }
 
+// Same, with the row ids known: prev_id = rows[s - 1] (-1 for s = 0), id = rows[s].
+template <typename AT>
+__device__ inline void zero_gaps_ids(const TtmcArgs& a, int s, int prev_id, int id, int lane) {
+    AT* Y = (AT*)a.Y;
+    const int64_t K = a.K;
+    for (int64_t e = (int64_t)(prev_id + 1) * K + lane; e < (int64_t)id * K; e += 64) Y[e] = AT(0);
+    if (s == a.S - 1)
+        for (int64_t e = (int64_t)(id + 1) * K + lane; e < (int64_t)a.In * K; e += 64) Y[e] = AT(0);
+}
+
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
@@ -269,15 +279,24 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
     f4_t acc = {0, 0, 0, 0};
 
     // the chunk owns every row it holds except a first row that started in an earlier chunk
+    // row ids of the rows a batch may touch, rows[rbase + lane] (a batch holds at most 16 rows),
+    // loaded one batch ahead; prev_id = id of the row before the one being finished
+    int rbase = s0;
+    int rowsv = ld_const(a.rows, min(s0 + lane, a.S - 1));
+    int prev_id = (s0 > 0) ? ld_const(a.rows, s0 - 1) : -1;
     auto flush = [&](int row) {
         const bool owner = (row != s0) || (slot < 0);
-        float* dst = owner ? (float*)a.Y + (int64_t)ld_const(a.rows, row) * K : (float*)a.carry + (int64_t)slot * K;
+        const int id = __builtin_amdgcn_readlane(rowsv, row - rbase);
+        const uint64_t base = owner ? (uint64_t)(uintptr_t)a.Y : (uint64_t)(uintptr_t)a.carry;
+        const int64_t off = owner ? (int64_t)id * K : (int64_t)slot * K;
+        float* dst = (float*)(uintptr_t)base + off;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = 4 * kq + v;
             if (r < Ra && m < Rb) dst[r * Rb + m] = acc[v];
         }
-        if (owner) zero_gaps<float>(a, row, lane);
+        if (owner) zero_gaps_ids<float>(a, row, prev_id, id, lane);
+        prev_id = id;
     };
     auto stream_load = [&](int pstart, int& ra, int& rb, float& rx) {
         const int qq = pstart + lane;
@@ -341,6 +360,9 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
         // 1. stage batch b+1 (past the chunk end: zero values at row 0), gather its rows, then the
         //    stream loads of batch b+3; the gathers fly while batch b runs
         const uint64_t starts_next = stage(xb ^ 1, r1a, r1b, r1x);
+        // first row of batch b+1: this batch's row plus the rows opened inside it
+        const int s_next = s + __popcll(starts & ~((p == q0) ? 1ull : 0ull));
+        const int rows_next = ld_const(a.rows, min(s_next + lane, a.S - 1));
         TK_GATHER()
         r1a = r2a; r1b = r2b; r1x = r2x;
         if (p + 192 < q1) stream_load(p + 192, r2a, r2b, r2x);
@@ -374,6 +396,8 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
         TK_PUT()
         starts = starts_next;
         xb ^= 1;
+        rbase = s_next;
+        rowsv = rows_next;
     }
     flush(s);
 #undef TK_G1
