@@ -316,9 +316,7 @@ __global__ __launch_bounds__(1024) void k_loss(const double* __restrict__ part, 
     __shared__ double red[1024];
     const int64_t per = (n + 1023) / 1024;
     const int64_t b = (int64_t)threadIdx.x * per, e = min(n, b + per);
-    double s = 0.0;
-    for (int64_t k = b; k < e; ++k) s += part[k];
-    red[threadIdx.x] = s;
+    red[threadIdx.x] = (e > b) ? sum_strided(part + b, (int)(e - b), 1) : 0.0;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
