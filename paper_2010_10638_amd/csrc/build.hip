@@ -364,6 +364,7 @@ int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t
     // chunk count: kChunkWavesPerCU resident waves per compute unit, pieces of at least 256 entries
     int ncu = 0;
     TK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    ctx->ncu = ncu;
     const int64_t nchunk_target =
         std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(ncu, 1) * kChunkWavesPerCU, D / 256));
     for (int m = 0; m < N; ++m) {

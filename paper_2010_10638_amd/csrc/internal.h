@@ -123,6 +123,7 @@ struct tk_ctx {
     tk::CompletionWs cws;
     hipStream_t last_stream = nullptr;
     int device = 0;
+    int ncu = 0;                     // compute units of the device
     // region timing of hooi_sweep (tucker_profile)
     hipEvent_t* prof_ev = nullptr;   // [capacity][4N + 2]
     int prof_cap = 0;

@@ -82,6 +82,163 @@ __global__ void k_gram_reduce(const double* __restrict__ part, int nsplit, int n
     if ((i >> 6) != (j >> 6)) C[(int64_t)j * n + i] = s;
 }
 
+// Wave-wide maximum / minimum, the result in every lane: butterflies inside each row of 16 lanes
+// through DPP (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror), then the
+// four row results through readlane.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ inline double wave_max_f64(double v) {
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x140>(v));
+    return fmax(fmax(wave_bcast(v, 15), wave_bcast(v, 31)), fmax(wave_bcast(v, 47), wave_bcast(v, 63)));
+}
+__device__ inline int wave_min_i32(int v) {
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false));
+    return min(min(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+               min(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
+}
+
+// Pivoted Cholesky of C for R <= RM steps with L (R x n) in LDS: the decisions and arithmetic of
+// k_pivchol below, with threads owning columns instead of positions.  Thread c keeps column c's
+// Schur-complement diagonal and its current position (pivoting swaps positions; among equal
+// maxima the lowest position wins).  Per step j, one barrier: each wave finds its candidate (the
+// maximum diagonal over positions >= j, then the lowest position holding it, by DPP reductions)
+// and posts it; after the barrier every thread picks the winner among the waves' candidates,
+// swaps positions, reads row cs of C for its column and the pivot column of L (all RM rows at
+// once, rows i >= j taken as zero, so the zero terms leave the sum unchanged), and writes its
+// new entry of L.  R11 is gathered from the pivot columns of L and
+// R11^{-1} formed by back substitution, thread c computing column c.
+template <int RM>
+__global__ __launch_bounds__(1024) void k_pivchol_cols(const double* __restrict__ C, int n, int R,
+                                                       double* __restrict__ R11, double* __restrict__ Rinv,
+                                                       int32_t* __restrict__ pivw, int32_t* __restrict__ flag) {
+    constexpr int kNone = 0x7fffffff;
+    extern __shared__ double Ls[];              // [RM][n], row i = L[i][*] by column id
+    __shared__ double s_v[2][16], s_d[2][16];
+    __shared__ int s_p[2][16], s_c[2][16];
+    __shared__ double s_mx[16];
+    __shared__ int s_piv[RM];
+    __shared__ double sR[RM][RM + 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nw = (int)(blockDim.x >> 6);
+    const bool valid = tid < n;
+    for (int e = tid; e < RM * n; e += blockDim.x) Ls[e] = 0.0;
+    double d = valid ? C[(int64_t)tid * n + tid] : -1.0;
+    int pos = valid ? tid : kNone;
+    {
+        const double v = wave_max_f64(d);
+        if (lane == 0) s_mx[wid] = v;
+    }
+    __syncthreads();
+    double dmax0 = s_mx[0];
+    for (int k = 1; k < nw; ++k) dmax0 = fmax(dmax0, s_mx[k]);
+    bool bad = false;
+    for (int j = 0; j < R; ++j) {
+        const int b = j & 1;
+        // the wave's candidate: maximum diagonal over positions >= j, lowest position holding it
+        const bool cand = pos >= j && pos != kNone;
+        const double v = cand ? d : -INFINITY;
+        const double mx = wave_max_f64(v);
+        const int lp = wave_min_i32((cand && v == mx) ? pos : kNone);
+        if (lp != kNone) {
+            const uint64_t h = __ballot(pos == lp);
+            const int o = (int)__builtin_ctzll(h);
+            const double dw = wave_bcast(d, o);
+            if (lane == 0) { s_v[b][wid] = mx; s_p[b][wid] = lp; s_c[b][wid] = wid * 64 + o; s_d[b][wid] = dw; }
+        } else if (lane == 0) {
+            s_v[b][wid] = -INFINITY; s_p[b][wid] = kNone; s_c[b][wid] = 0; s_d[b][wid] = 0.0;
+        }
+        __syncthreads();
+        double bv = s_v[b][0];
+        int bp = s_p[b][0], cs = s_c[b][0];
+        double djj = s_d[b][0];
+        for (int k = 1; k < nw; ++k) {
+            const double v2 = s_v[b][k];
+            const int p2 = s_p[b][k];
+            if (v2 > bv || (v2 == bv && p2 < bp)) { bv = v2; bp = p2; cs = s_c[b][k]; djj = s_d[b][k]; }
+        }
+        if (bp == kNone) {
+            // no comparable candidate (NaN): position j stays; its column and diagonal
+            bp = j;
+            const uint64_t h = __ballot(pos == j);
+            if (h) {
+                const int o = (int)__builtin_ctzll(h);
+                s_c[b][0] = wid * 64 + o;   // one wave holds position j
+                s_d[b][0] = wave_bcast(d, o);
+            }
+            __syncthreads();
+            cs = s_c[b][0];
+            djj = s_d[b][0];
+        }
+        if (pos == bp) pos = j;
+        else if (pos == j) pos = bp;
+        if (!(djj > 1e-12 * dmax0)) bad = true;
+        const double ljj = bad ? 1.0 : sqrt(djj);
+        double acc = C[(int64_t)cs * n + (valid ? tid : 0)];
+        // rows i >= j read as zero (row j of the pivot column may already hold ljj)
+        double lc[RM], lp2[RM];
+#pragma unroll
+        for (int i = 0; i < RM; ++i) {
+            const double a0 = Ls[i * n + (valid ? tid : 0)];
+            const double a1 = Ls[i * n + cs];
+            lc[i] = (i < j) ? a0 : 0.0;
+            lp2[i] = (i < j) ? a1 : 0.0;
+        }
+        if (tid == cs) {
+            Ls[j * n + cs] = ljj;
+        } else if (valid && pos > j) {
+#pragma unroll
+            for (int i = 0; i < RM; ++i) acc -= lc[i] * lp2[i];
+            const double l = acc / ljj;
+            Ls[j * n + tid] = l;
+            d -= l * l;
+        }
+    }
+    if (pos < R) s_piv[pos] = tid;
+    __syncthreads();
+    for (int e = tid; e < R * R; e += blockDim.x) {
+        const int i = e / R, jj = e % R;
+        const double r = (i <= jj) ? Ls[i * n + s_piv[jj]] : 0.0;
+        R11[e] = r;
+        sR[i][jj] = r;
+    }
+    if (tid < R) pivw[tid] = s_piv[tid];
+    __syncthreads();
+    // column c of R11^{-1} in thread c: x_k = b_k / r_kk for k = c down to 0, removing each x_k
+    // from the rows above it
+    if (tid < R) {
+        double bb[RM], x[RM];
+#pragma unroll
+        for (int i = 0; i < RM; ++i) {
+            bb[i] = (i == tid) ? 1.0 : 0.0;
+            x[i] = 0.0;
+        }
+#pragma unroll
+        for (int k = RM - 1; k >= 0; --k) {
+            if (k <= tid) {
+                x[k] = bb[k] / sR[k][k];
+#pragma unroll
+                for (int i = 0; i < k; ++i) bb[i] -= sR[i][k] * x[k];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+            if (i < R) Rinv[i * R + tid] = (i <= tid) ? x[i] : 0.0;
+    }
+    if (tid == 0) *flag = bad ? 1 : 0;
+}
+
 // Pivoted Cholesky of C (n <= 1024), R steps, one workgroup of ceil(n/64) waves; thread t owns
 // position t of the (physically swapped) column order and keeps that position's column id and
 // Schur-complement diagonal in registers.  Per step: a block argmax (first maximum) of the
@@ -578,8 +735,9 @@ QrpPlan plan(const tk_ctx* ctx, int mode) {
         const int64_t nn = (int64_t)p.n * p.n;
         int64_t cap = std::max<int64_t>(1, (int64_t)(32u << 20) / 8 / nn);  // <= 32 MB of partials
         const int64_t pairs = (int64_t)p.nb * (p.nb + 1) / 2;
-        const int64_t want = std::max<int64_t>(1, 768 / pairs);   // about 768 workgroups
-        p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(p.m + 127) / 128, want, cap}));
+        // one round of workgroups: two per compute unit (each stages 66 KB in LDS)
+        const int64_t want = std::max<int64_t>(1, 2 * (int64_t)std::max(ctx->ncu, 1) / pairs);
+        p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(p.m + 31) / 32, want, cap}));
         p.slab = ((p.m + p.nsplit - 1) / p.nsplit + 31) / 32 * 32;
         p.nsplit = (int)((p.m + p.slab - 1) / p.slab);
         p.rows2 = 64;
@@ -623,7 +781,13 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
         TK_LAUNCH_CHECK("k_gram_reduce");
         const size_t lsz = (size_t)p.n * p.R * sizeof(double);
         const unsigned nthr = (unsigned)std::max(64, (p.n + 63) / 64 * 64);
-        if (lsz <= 64 * 1024)
+        if (p.R <= 16 && (size_t)p.n * 16 * sizeof(double) <= 64 * 1024)
+            k_pivchol_cols<16><<<1, nthr, (size_t)p.n * 16 * sizeof(double), s>>>(W + p.o_C, p.n, p.R, W + p.o_R11,
+                                                                              W + p.o_Rinv, pivw, flag);
+        else if (p.R <= 32 && (size_t)p.n * 32 * sizeof(double) <= 64 * 1024)
+            k_pivchol_cols<32><<<1, nthr, (size_t)p.n * 32 * sizeof(double), s>>>(W + p.o_C, p.n, p.R, W + p.o_R11,
+                                                                              W + p.o_Rinv, pivw, flag);
+        else if (lsz <= 64 * 1024)
             k_pivchol<true><<<1, nthr, lsz, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, W + p.o_R11, W + p.o_Rinv, pivw, flag);
         else
             k_pivchol<false><<<1, nthr, 0, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, W + p.o_R11, W + p.o_Rinv, pivw, flag);

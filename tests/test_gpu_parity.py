@@ -143,6 +143,50 @@ def test_ttmc_parity(tk, dtype, case):
         assert rel_fro(Y, Yc) <= (1e-13 if dtype == "f64" else 2e-6), (mode, rel_fro(Y, Yc))
 
 
+def long_row_case(seed):
+    """Mode 0 with rows of very different lengths averaging well over 256 entries: long rows
+    that span several chunks, and runs of 1-4 entry rows, so that up to four rows start inside
+    one 16-entry group."""
+    rng = np.random.default_rng(seed)
+    dims, ranks = [120, 400, 300], [16, 12, 10]
+    lens = np.zeros(dims[0], dtype=np.int64)
+    lens[::7] = rng.integers(1500, 4000, size=lens[::7].size)
+    short = np.setdiff1d(np.arange(dims[0]), np.arange(0, dims[0], 7))
+    lens[short[: 60]] = rng.integers(1, 5, size=60)   # the rest stay empty
+    coords = []
+    for i, n in enumerate(lens):
+        if n == 0:
+            continue
+        keys = rng.choice(dims[1] * dims[2], size=int(n), replace=False)
+        coords.append(np.stack([np.full(n, i), keys // dims[2], keys % dims[2]]))
+    coords = np.concatenate(coords, axis=1).astype(np.int32)
+    vals = rng.standard_normal(coords.shape[1])
+    U = [synth.gaussian_qr(rng, d, r) for d, r in zip(dims, ranks)]
+    return dims, ranks, coords, vals, U
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_ttmc_long_rows(tk, dtype):
+    dims, ranks, coords, vals, U = long_row_case(21)
+    ctx = tk.tucker_init(*to_dev(coords, vals), dims, ranks, dtype=dtype)
+    info = tk.tucker_get_info(ctx)
+    assert info["nnz"] >= 256 * info["rows"][0]
+    Ud = dev_list(U)
+    Y = tk.ttmc_mode(ctx, 0, Ud)
+    Y2 = tk.ttmc_mode(ctx, 0, Ud)
+    assert torch.equal(Y, Y2)   # deterministic
+    Y = Y.double().cpu().numpy()
+    Yo = oracle.ttmc(coords, vals, dims, ranks, 0, U)
+    assert rel_fro(Y, Yo) <= TOL_Y[dtype]
+    Yc = oracle.ttmc(coords, cast_vals(vals, dtype), dims, ranks, 0, cast_inputs(U, dtype))
+    assert rel_fro(Y, Yc) <= 2e-6
+    # rows: every non-empty row matches on its own (short rows next to long ones), empty rows are 0
+    lens = np.bincount(coords[0], minlength=dims[0])
+    for i in np.flatnonzero(lens):
+        assert rel_fro(Y[i], Yc[i]) <= 2e-5, (i, lens[i])
+    assert np.all(Y[lens == 0] == 0)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_ttmc_degenerate(tk, dtype):
     # a single nonzero; all nonzeros in one row; rank-1 factors
@@ -227,6 +271,27 @@ def test_qrp_rank_deficient_fallback(tk):
     assert piv.cpu().numpy()[:3].tolist() == pe[:3].tolist()
     np.testing.assert_allclose(U.T @ U, np.eye(5), atol=1e-12)
     np.testing.assert_allclose(U[:, :3] @ (U[:, :3].T @ Y), Y, atol=1e-9 * np.abs(Y).max())
+
+
+@pytest.mark.parametrize("K", [64, 256])
+def test_qrp_tied_norms(tk, K):
+    """Columns 3 and 7 of Y have exactly equal norms (7 is 3 with half its entries negated) and the
+    largest norm, so the first pivot is a tie: as in Householder QRP with column swaps, the lower
+    position wins on both sides; later steps then split the pair."""
+    rng = np.random.default_rng(12)
+    dims, ranks = [2000, 8, K // 8], [12, 8, K // 8]
+    w = synth.small_uniform(9, dims, ranks, 100)
+    ctx = make(tk, w, "f64")
+    Y = rng.standard_normal((2000, K))
+    Y[:, 3] *= 3.0
+    Y[:, 7] = Y[:, 3]
+    Y[::2, 7] *= -1.0
+    assert np.sum(Y[:, 3] ** 2) == np.sum(Y[:, 7] ** 2)
+    U, piv = tk.qrp_update(ctx, 0, torch.from_numpy(Y).cuda())
+    Ue, pe = oracle.factor(Y, 12)
+    assert pe[0] == 3
+    assert piv.cpu().numpy().tolist() == pe.tolist()
+    np.testing.assert_allclose(U.cpu().numpy(), Ue, atol=1e-10)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
