@@ -151,11 +151,15 @@ __global__ __launch_bounds__(1024) void k_pivchol_cols(const double* __restrict_
         const double v = cand ? d : -INFINITY;
         const double mx = wave_max_f64(v);
         const int lp = wave_min_i32((cand && v == mx) ? pos : kNone);
+        double touch = 0.0;
         if (lp != kNone) {
             const uint64_t h = __ballot(pos == lp);
             const int o = (int)__builtin_ctzll(h);
             const double dw = wave_bcast(d, o);
             if (lane == 0) { s_v[b][wid] = mx; s_p[b][wid] = lp; s_c[b][wid] = wid * 64 + o; s_d[b][wid] = dw; }
+            // start fetching the candidate's row of C (one load per 32 bytes) while the waves
+            // compare: the winner's row is then in this CU's cache when it is read below
+            touch = C[(int64_t)(wid * 64 + o) * n + min(4 * lane, n - 1)];
         } else if (lane == 0) {
             s_v[b][wid] = -INFINITY; s_p[b][wid] = kNone; s_c[b][wid] = 0; s_d[b][wid] = 0.0;
         }
@@ -204,6 +208,7 @@ __global__ __launch_bounds__(1024) void k_pivchol_cols(const double* __restrict_
             Ls[j * n + tid] = l;
             d -= l * l;
         }
+        asm volatile("" ::"v"(touch));   // keeps the prefetch (complete by now: loads retire in order)
     }
     if (pos < R) s_piv[pos] = tid;
     __syncthreads();
@@ -424,13 +429,15 @@ __global__ __launch_bounds__(64) void k_qrp_finish(const YT* __restrict__ Y, int
     const int lane = threadIdx.x;
     const bool live = lane < R;
     const int lr = live ? lane : 0;
-    double w[RMAX], t[RMAX];
-    // lane c: column c of G2; lane i: row i of R11^{-1} (t) - loads in flight together
+    double w[RMAX], t[RMAX], yv[RMAX];
+    // lane c: column c of G2; lane i: row i of R11^{-1} (t) and row i of Y[0:R, piv] (yv) - loads
+    // in flight together
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
         const int kk = k < R ? k : 0;
         w[k] = G2in[kk * R + lr];
         t[k] = Rinv[lr * R + kk];
+        yv[k] = yld(Y, (int64_t)lr * n + pivw[kk]);
     }
     bool bad = false;
     // Cholesky, right-looking: after step j, w[j] of lane c is R2[j][c]
@@ -464,9 +471,9 @@ __global__ __launch_bounds__(64) void k_qrp_finish(const YT* __restrict__ Y, int
 #pragma unroll
     for (int c = 0; c < RMAX; ++c)
         if (live && c < R) sM[lane][c] = t[c];
-    // row i of Y[0:R, piv] (w), then row i of T = Y[0:R, piv] M' (t)
+    // row i of T = Y[0:R, piv] M' (t)
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) w[k] = yld(Y, (int64_t)lr * n + pivw[k < R ? k : 0]);
+    for (int k = 0; k < RMAX; ++k) w[k] = yv[k];
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
