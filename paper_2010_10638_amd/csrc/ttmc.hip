@@ -669,7 +669,9 @@ __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
     flush_row();
 }
 
-// Adds the carry slots of each split row, in slot order, to the row written by its owner.
+// Adds the carry slots of each split row, in slot order, to the row written by its owner.  The
+// loads are issued eight slots at a time (a hot row can span hundreds of pieces); the additions
+// keep slot order.
 template <typename AT>
 __global__ __launch_bounds__(256) void k_ttmc_fixup(const int32_t* __restrict__ split,
                                                     const int32_t* __restrict__ rows, int K,
@@ -679,7 +681,15 @@ __global__ __launch_bounds__(256) void k_ttmc_fixup(const int32_t* __restrict__ 
     AT* y = Y + (int64_t)rows[s] * K;
     for (int c = threadIdx.x; c < K; c += blockDim.x) {
         AT acc = AT(0);
-        for (int k = f; k <= l; ++k) acc += carry[(int64_t)k * K + c];
+        int k = f;
+        for (; k + 8 <= l + 1; k += 8) {
+            AT v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = carry[(int64_t)(k + u) * K + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        for (; k <= l; ++k) acc += carry[(int64_t)k * K + c];
         y[c] += acc;
     }
 }
