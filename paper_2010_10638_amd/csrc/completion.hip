@@ -278,8 +278,8 @@ template <typename AT>
 __global__ __launch_bounds__(256) void k_gg_partial(const AT* __restrict__ Y, const AT* __restrict__ U,
                                                     int64_t I, int K, int R, int64_t slab,
                                                     double* __restrict__ part) {
-    __shared__ double As[2][32][65];
-    __shared__ double Bs[2][32][65];
+    __shared__ AT As[2][32][65];
+    __shared__ AT Bs[2][32][65];
     const int b0 = blockIdx.x * 64, a0 = blockIdx.z * 64;
     const int64_t r0 = (int64_t)blockIdx.y * slab;
     const int64_t r1 = min(I, r0 + slab);

@@ -46,8 +46,8 @@ __device__ inline double yld(const YT* Y, int64_t i) { return (double)Y[i]; }
 template <typename YT>
 __global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, int64_t m, int n,
                                                       int nb, int64_t slab, double* __restrict__ part) {
-    __shared__ double As[2][32][65];
-    __shared__ double Bs[2][32][65];
+    __shared__ YT As[2][32][65];
+    __shared__ YT Bs[2][32][65];
     int b = blockIdx.x, bi = 0;
     while (b >= nb - bi) { b -= nb - bi; ++bi; }
     const int bj = bi + b;
