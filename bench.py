@@ -242,6 +242,9 @@ def main():
                     "R 8, FP64; skewed-*: 500,000 x 100,000 x 365, 50M Zipf nnz, R 10; order4-*: "
                     "50,000 x 50,000 x 5,000 x 100, 20M nnz, R 8; completion: 100,000 x 100,000 x 1,000, "
                     "30M entries, R 16, one Adam step of the completion loss per step")
+    ap.add_argument("--factor", default="qrp", choices=["qrp", "svd"],
+                    help="factor update of the HOOI sweeps: qrp (Alg. 2, default) or svd (Alg. 1, the "
+                    "leading left singular vectors; not the bench line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (calibrates FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--compare-precisions", action="store_true",
@@ -302,7 +305,7 @@ def main():
         return compare_precisions(args, w, tk, torch)
     coords = torch.from_numpy(w.coords).cuda()
     vals = torch.from_numpy(w.vals).cuda()
-    ctx = tk.tucker_init(coords, vals, w.dims, w.ranks, dtype=w.dtype)
+    ctx = tk.tucker_init(coords, vals, w.dims, w.ranks, dtype=w.dtype, svd=args.factor == "svd")
     del coords, vals
     info = tk.tucker_get_info(ctx)
     U = [torch.from_numpy(u).cuda() for u in w.U_init]
@@ -333,7 +336,7 @@ def main():
     value = upd_per_sweep / sweep_s
 
     # dominant kernel: the TTMc (one launch per mode per sweep)
-    default = args.workload == "lowrank" and not args.small
+    default = args.workload == "lowrank" and not args.small and args.factor == "qrp"
     val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[w.dtype]
     fac_bytes = val_bytes
     y_bytes = 8 if w.dtype == "f64" else 4
@@ -349,7 +352,7 @@ def main():
     core_s = prof["core_ms"] / 1e3 / prof["sweeps"]
 
     out = {
-        "metric": "TTMc nnz*prod(R) updates/s over whole HOOI sweeps (TTMc + FP64 QRP + core)",
+        "metric": "TTMc nnz*prod(R) updates/s over whole HOOI sweeps (TTMc + FP64 %s + core)" % args.factor.upper(),
         "value": value,
         "unit": "updates/s",
         "n_gpus": 1,
@@ -362,7 +365,7 @@ def main():
         "dtype": w.dtype,
         "data": "synthetic",
         "config": {"workload": w.name, "dims": w.dims, "ranks": w.ranks, "nnz": nnz,
-                   "ttmc": w.dtype, "qrp": "f64", "parallelism": "single-gpu"},
+                   "ttmc": w.dtype, "qrp": "f64", "factor_update": args.factor, "parallelism": "single-gpu"},
         "roofline": roofline(w, N, flops, bytes_, t_launch, default),
         "breakdown_ms_per_sweep": {"ttmc": ttmc_s * 1e3, "qrp": qrp_s * 1e3, "core_fit": core_s * 1e3,
                                    "ttmc_per_mode": [x / prof["sweeps"] for x in prof["ttmc_ms"]],

@@ -54,6 +54,7 @@ enum tk_dtype { TK_F64 = 0, TK_F32 = 1, TK_BF16 = 2 };
 
 /* tucker_init flags */
 #define TK_FLAG_NO_FAT_RULE 0x1u     /* factor a fat Y_(n) directly instead of Y_(n) Y_(n)^T */
+#define TK_FLAG_SVD         0x2u     /* hooi_sweep updates each factor by svd_update (Alg. 1) */
 
 #define TK_MAX_ORDER 8               /* 2 <= N <= TK_MAX_ORDER */
 #define TK_MAX_KCOLS 4096            /* K_n = prod_{t != n} R_t must not exceed this */
@@ -124,6 +125,21 @@ int ttmc_mode(tk_ctx* ctx, int mode, const double* const* U, void* Y, void* stre
 int qrp_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, int32_t* piv, void* stream);
 
 /*
+ * svd_update - U_n <- the R_n leading left singular vectors of Y_(n) (the SVD update of standard
+ * HOOI, Alg. 1; Sec. III-D contrasts it with the QRP), in FP64.  Computed from the
+ * eigendecomposition of Y_(n)^T Y_(n) (K_n <= I_n; columns Y v / sigma) or of Y_(n) Y_(n)^T
+ * (fat rule), formed in FP64 on the device.  Columns are ordered by decreasing singular value;
+ * each column's entry of largest magnitude (the first one on ties) is positive.  A zero singular
+ * value gives a zero column.
+ *   Y     device I_n x K_n (double for TK_F64, float otherwise)
+ *   U_out device double I_n x R_n
+ * Shapes the QRP handles only by Householder (R_n > 32, or K_n > 1024 on a tall Y_(n), or a fat
+ * Y_(n) with TK_FLAG_NO_FAT_RULE) return TK_ERR_UNSUPPORTED.  The eigensolver's convergence flag
+ * stays on the device.  Also refreshes the context's low-precision copy of U_n.
+ */
+int svd_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, void* stream);
+
+/*
  * core_fit - G_(N) = U_N^T Y_(N) (Alg. 2, the step after the mode loop) and the fit.
  *   Y_last device I_N x K_N (context Y type) computed with the final U_1..U_{N-1}
  *   U_last device double I_N x R_N (orthonormal columns)
@@ -136,7 +152,8 @@ int core_fit(tk_ctx* ctx, const void* Y_last, const double* U_last, double* G, d
 /*
  * hooi_sweep - one sweep of Alg. 2: for n = 0..N-1, TTMc with the current factors then
  * U_n <- QRP(Y_(n), R_n) (modes updated in order, each using the factors already refreshed in this
- * sweep); then the core and the fit.
+ * sweep); then the core and the fit.  A context created with TK_FLAG_SVD updates the factors with
+ * svd_update instead (Alg. 1).
  *   U        host array of N device pointers to double I_k x R_k, read and overwritten
  *   G        device double[prod R_k] (C-order), overwritten
  *   fit_dev  device double scalar or NULL

@@ -17,10 +17,11 @@ LIB_PATH = os.path.join(_HERE, "lib", "libsptucker.so")
 TK_OK, TK_ERR_ARG, TK_ERR_RANGE, TK_ERR_OOM, TK_ERR_HIP, TK_ERR_UNSUPPORTED = range(6)
 TK_F64, TK_F32, TK_BF16 = 0, 1, 2
 TK_FLAG_NO_FAT_RULE = 0x1
+TK_FLAG_SVD = 0x2
 DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
 _STATUS = {1: "TK_ERR_ARG", 2: "TK_ERR_RANGE", 3: "TK_ERR_OOM", 4: "TK_ERR_HIP", 5: "TK_ERR_UNSUPPORTED"}
 
-EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "core_fit",
+EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "svd_update", "core_fit",
            "hooi_sweep", "reconstruct", "ttmc_adjoint", "tucker_profile", "tucker_profile_read", "tucker_free",
            "tucker_last_error")
 
@@ -49,6 +50,7 @@ def load_library(path: str = LIB_PATH):
     lib.tucker_get_csf.argtypes = [P, I, P, P, P, P, P]
     lib.ttmc_mode.argtypes = [P, I, P, P, P]
     lib.qrp_update.argtypes = [P, I, P, P, P, P]
+    lib.svd_update.argtypes = [P, I, P, P, P]
     lib.core_fit.argtypes = [P, P, P, P, P, P]
     lib.hooi_sweep.argtypes = [P, P, P, P, P, P]
     lib.reconstruct.argtypes = [P, P, P, I64, P, P, P]
@@ -123,8 +125,9 @@ class Ctx:
 
 
 def tucker_init(coords: torch.Tensor, vals: torch.Tensor, dims, ranks, dtype: str = "f32",
-                fat_rule: bool = True) -> Ctx:
-    """coords: int32 [N, nnz] (0-based), vals: float64 [nnz], both on the GPU."""
+                fat_rule: bool = True, svd: bool = False) -> Ctx:
+    """coords: int32 [N, nnz] (0-based), vals: float64 [nnz], both on the GPU.  svd: hooi_sweep
+    updates the factors by svd_update instead of qrp_update."""
     lib = load_library()
     N = len(dims)
     if coords.dim() != 2 or coords.shape[0] != N:
@@ -135,7 +138,7 @@ def tucker_init(coords: torch.Tensor, vals: torch.Tensor, dims, ranks, dtype: st
     d = (ctypes.c_int64 * N)(*[int(x) for x in dims])
     r = (ctypes.c_int32 * N)(*[int(x) for x in ranks])
     h = ctypes.c_void_p()
-    flags = 0 if fat_rule else TK_FLAG_NO_FAT_RULE
+    flags = (0 if fat_rule else TK_FLAG_NO_FAT_RULE) | (TK_FLAG_SVD if svd else 0)
     cp = _dev(coords, torch.int32, "coords") if nnz else None
     vp = _dev(vals, torch.float64, "vals") if nnz else None
     _check(lib.tucker_init(ctypes.byref(h), N, d, r, nnz, cp, vp, DTYPES[dtype], flags, _stream()))
@@ -187,6 +190,14 @@ def qrp_update(ctx: Ctx, mode: int, Y: torch.Tensor, U_out: torch.Tensor | None 
                                      _dev(U_out, torch.float64, "U_out"), _dev(piv, torch.int32, "piv"),
                                      _stream()))
     return U_out, piv
+
+
+def svd_update(ctx: Ctx, mode: int, Y: torch.Tensor, U_out: torch.Tensor | None = None):
+    if U_out is None:
+        U_out = torch.empty((ctx.dims[mode], ctx.ranks[mode]), dtype=torch.float64, device="cuda")
+    _check(load_library().svd_update(ctx.handle, mode, _dev(Y, ctx.ytype, "Y"),
+                                     _dev(U_out, torch.float64, "U_out"), _stream()))
+    return U_out
 
 
 def core_fit(ctx: Ctx, Y_last: torch.Tensor, U_last: torch.Tensor, G: torch.Tensor | None = None,

@@ -57,6 +57,7 @@ void free_ctx(tk_ctx* c) {
     if (!c) return;
     free_events(c);
     free_completion_ws(c);
+    free_svd_ws(c);
     for (int m = 0; m < kMaxOrder; ++m) {
         ModeLayout& ml = c->mode[m];
         void* ps[] = {ml.rows, ml.ptr, ml.pptr, ml.idx, ml.val, ml.chunk_ptr, ml.chunk_row, ml.chunk_slot, ml.split};
@@ -106,7 +107,7 @@ int tucker_init(tk_ctx** out, int order, const int64_t* dims, const int32_t* ran
     if (nnz < 0) return set_error(TK_ERR_ARG, "negative nnz");
     if (nnz >= (int64_t)1 << 31) return set_error(TK_ERR_UNSUPPORTED, "nnz %lld >= 2^31", (long long)nnz);
     if (nnz > 0 && (!coords || !vals)) return set_error(TK_ERR_ARG, "coords/vals is null");
-    if (flags & ~TK_FLAG_NO_FAT_RULE) return set_error(TK_ERR_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(TK_FLAG_NO_FAT_RULE | TK_FLAG_SVD)) return set_error(TK_ERR_ARG, "unknown flags 0x%x", flags);
     double log2prod = 0.0;
     for (int t = 0; t < order; ++t) {
         if (dims[t] < 1) return set_error(TK_ERR_ARG, "dims[%d] = %lld < 1", t, (long long)dims[t]);
@@ -229,6 +230,17 @@ int qrp_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, int32_t* piv
     return st;
 }
 
+int svd_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, void* stream) {
+    int st = check_ctx(ctx);
+    if (st || (st = check_mode(ctx, mode))) return st;
+    if (!Y || !U_out) return set_error(TK_ERR_ARG, "Y/U_out is null");
+    if ((st = pending_error())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = svd_run(ctx, mode, Y, U_out, s);
+    ctx->last_stream = s;
+    return st;
+}
+
 int core_fit(tk_ctx* ctx, const void* Y_last, const double* U_last, double* G, double* fit, void* stream) {
     int st = check_ctx(ctx);
     if (st) return st;
@@ -262,7 +274,9 @@ int hooi_sweep(tk_ctx* ctx, double* const* U, double* G, double* fit_dev, double
         if (ev) TK_HIP(hipEventRecord(ev[2 * n], s));
         if ((st = ttmc_run(ctx, n, ctx->ws.y, s, ev ? ev + 2 * N + 2 + 2 * n : nullptr))) return st;
         if (ev) TK_HIP(hipEventRecord(ev[2 * n + 1], s));
-        if ((st = qrp_run(ctx, n, ctx->ws.y, U[n], nullptr, s))) return st;
+        st = (ctx->flags & TK_FLAG_SVD) ? svd_run(ctx, n, ctx->ws.y, U[n], s)
+                                        : qrp_run(ctx, n, ctx->ws.y, U[n], nullptr, s);
+        if (st) return st;
     }
     if (ev) TK_HIP(hipEventRecord(ev[2 * ctx->N], s));
     if ((st = core_run(ctx, ctx->ws.y, U[ctx->N - 1], G, fit, s))) return st;

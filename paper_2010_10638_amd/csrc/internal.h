@@ -121,6 +121,11 @@ struct tk_ctx {
     int ldU[tk::kMaxOrder] = {};
     tk::Workspace ws;
     tk::CompletionWs cws;
+    // SVD factor update: rocBLAS handle and eigen-solver workspace (allocated on first use)
+    void* rb = nullptr;
+    double* svd_d = nullptr;         // eigenvalues, TK_MAX_KCOLS
+    double* svd_e = nullptr;         // off-diagonal workspace, TK_MAX_KCOLS
+    int32_t* svd_info = nullptr;
     hipStream_t last_stream = nullptr;
     int device = 0;
     int ncu = 0;                     // compute units of the device
@@ -194,6 +199,11 @@ void free_completion_ws(tk_ctx* ctx);
 
 // QRP (qrp.hip): Y -> U (FP64) and the low-precision copy ctx->Ulp[mode]
 int qrp_run(tk_ctx* ctx, int mode, const void* Y, double* U, int32_t* piv, hipStream_t s);
+// FP64 Y^T Y (tall) or Y Y^T (fat) of a mode in the QRP workspace: *A (n x n, full), *n
+int gram_run(tk_ctx* ctx, int mode, const void* Y, double** A, int* n, hipStream_t s);
+// SVD factor update (svd.hip): U <- leading R_n left singular vectors of Y_(n)
+int svd_run(tk_ctx* ctx, int mode, const void* Y, double* U, hipStream_t s);
+void free_svd_ws(tk_ctx* ctx);
 size_t qrp_workspace_bytes(const tk_ctx* ctx, int mode);
 int qrp_route(const tk_ctx* ctx, int mode);
 

@@ -834,6 +834,40 @@ size_t qrp_workspace_bytes(const tk_ctx* ctx, int mode) { return (size_t)plan(ct
 
 int qrp_route(const tk_ctx* ctx, int mode) { return plan(ctx, mode).route; }
 
+// The symmetric FP64 matrix the factor update of this mode works on: Y^T Y (K_n x K_n, the Gram
+// kernels) when Y_(n) is tall, Y Y^T (I_n x I_n) when the fat rule applies; full storage in the
+// QRP workspace.  Shapes without a Gram route (R_n > 32 or K_n > 1024 on a tall Y) are refused.
+template <typename YT>
+int gram_typed(tk_ctx* ctx, int mode, const YT* Y, double** A, int* n, hipStream_t s) {
+    const QrpPlan p = plan(ctx, mode);
+    double* W = ctx->ws.qrp;
+    if (p.route == 0) {
+        dim3 g1((unsigned)(p.nb * (p.nb + 1) / 2), (unsigned)p.nsplit);
+        k_gram_partial<YT><<<g1, 256, 0, s>>>(Y, p.m, p.n, p.nb, p.slab, W + p.o_part);
+        TK_LAUNCH_CHECK("k_gram_partial");
+        k_gram_reduce<<<cdiv((int64_t)p.n * p.n, 256), 256, 0, s>>>(W + p.o_part, p.nsplit, p.n, W + p.o_C);
+        TK_LAUNCH_CHECK("k_gram_reduce");
+        *A = W + p.o_C;
+        *n = p.n;
+        return TK_OK;
+    }
+    if (p.route == 2) {
+        const int64_t I = ctx->dims[mode];
+        k_syrk_rows<YT><<<cdiv(I * I, 256), 256, 0, s>>>(Y, (int)I, (int)ctx->mode[mode].K, W + p.o_A);
+        TK_LAUNCH_CHECK("k_syrk_rows");
+        *A = W + p.o_A;
+        *n = (int)I;
+        return TK_OK;
+    }
+    return set_error(TK_ERR_UNSUPPORTED, "mode %d: no Gram route for R_n = %d, K_n = %lld", mode, p.R,
+                     (long long)ctx->mode[mode].K);
+}
+
+int gram_run(tk_ctx* ctx, int mode, const void* Y, double** A, int* n, hipStream_t s) {
+    if (ctx->dtype == TK_F64) return gram_typed<double>(ctx, mode, (const double*)Y, A, n, s);
+    return gram_typed<float>(ctx, mode, (const float*)Y, A, n, s);
+}
+
 int qrp_run(tk_ctx* ctx, int mode, const void* Y, double* U, int32_t* piv, hipStream_t s) {
     switch (ctx->dtype) {
         case TK_F64: return run_typed<double, double>(ctx, mode, (const double*)Y, U, piv, s);

@@ -1,0 +1,85 @@
+"""GPU parity of the SVD factor update (standard HOOI, paper Alg. 1) against the oracle's LAPACK SVD,
+through the C ABI.  Singular vectors are compared after the library's sign convention (largest-
+magnitude entry of each column positive, first one on ties) is applied to the oracle's."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_10638_amd as tk_mod
+    tk_mod.load_library()
+    return tk_mod
+
+
+def signed(U):
+    U = np.array(U, dtype=np.float64, copy=True)
+    for r in range(U.shape[1]):
+        i = int(np.argmax(np.abs(U[:, r])))
+        if U[i, r] < 0:
+            U[:, r] = -U[:, r]
+    return U
+
+
+def make(tk, w, dtype, svd=False):
+    c = torch.from_numpy(np.ascontiguousarray(w.coords, dtype=np.int32)).cuda()
+    v = torch.from_numpy(np.ascontiguousarray(w.vals, dtype=np.float64)).cuda()
+    return tk.tucker_init(c, v, w.dims, w.ranks, dtype=dtype, svd=svd)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", [
+    ([3000, 40, 30], [12, 8, 8], 0, 20000),        # tall, K = 64
+    ([2000, 60, 50], [16, 16, 16], 0, 30000),      # tall, K = 256
+    ([900, 30, 40], [24, 16, 20], 0, 30000),       # tall, K = 320, R = 24
+    ([20, 30, 25, 40], [5, 4, 4, 4], 0, 6000),     # fat (K = 64 > 20): eigenvectors of Y Y^T
+])
+def test_svd_update_parity(tk, dtype, case):
+    dims, ranks, mode, nnz = case
+    w = synth.small_uniform(300, dims, ranks, nnz)
+    ctx = make(tk, w, dtype)
+    Yo = oracle.ttmc(w.coords, w.vals, dims, ranks, mode, w.U_init)
+    yt = torch.float64 if dtype == "f64" else torch.float32
+    Yd = torch.from_numpy(Yo).to(yt).cuda().contiguous()
+    U = tk.svd_update(ctx, mode, Yd).cpu().numpy()
+    Ue = signed(oracle.svd_factor(Yd.double().cpu().numpy(), ranks[mode]))
+    np.testing.assert_allclose(U, Ue, atol=1e-9)
+    np.testing.assert_allclose(U.T @ U, np.eye(ranks[mode]), atol=1e-10)
+
+
+def test_svd_hooi_sweeps_f64(tk):
+    """SVD-HOOI sweeps: fits match the oracle's and never decrease (each mode step maximises
+    ||U_n^T Y_(n)|| exactly, which is what makes the fit monotone for the SVD variant)."""
+    dims, ranks = [120, 100, 80], [6, 5, 4]
+    w = synth.small_uniform(31, dims, ranks, 15000)
+    Uo, Go, fo = oracle.hooi_svd(w.coords, w.vals, dims, ranks, w.U_init, 5)
+    ctx = make(tk, w, "f64", svd=True)
+    U = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in w.U_init]
+    fits = []
+    for _ in range(5):
+        G, f = tk.hooi_sweep(ctx, U, sync_fit=True)
+        fits.append(f)
+    np.testing.assert_allclose(fits, fo, rtol=1e-10, atol=0)
+    assert all(b >= a - 1e-13 for a, b in zip(fits, fits[1:])), fits
+    for k in range(3):
+        np.testing.assert_allclose(U[k].cpu().numpy(), signed(Uo[k]), atol=1e-9)
+    # the core depends on the factors' signs; its norm (hence the fit) does not
+    assert abs(np.linalg.norm(G.cpu().numpy()) - np.linalg.norm(Go)) <= 1e-10 * np.linalg.norm(Go)
+
+
+def test_svd_unsupported_shape(tk):
+    """R_n > 32 on a tall Y has no Gram route: refused with TK_ERR_UNSUPPORTED."""
+    w = synth.small_uniform(5, [400, 40, 40], [34, 6, 6], 8000)
+    ctx = make(tk, w, "f64")
+    Y = torch.zeros((400, 36), dtype=torch.float64, device="cuda")
+    with pytest.raises(tk.TuckerError) as e:
+        tk.svd_update(ctx, 0, Y)
+    assert e.value.status == 5
