@@ -164,6 +164,20 @@ int hooi_sweep(tk_ctx* ctx, double* const* U, double* G, double* fit_dev, double
                void* stream);
 
 /*
+ * hooi_run - the outer loop of Alg. 2 with a stopping rule (the paper iterates "until
+ * convergence" without stating one; here: stop after sweep s >= 1 when |fit_s - fit_{s-1}| <= tol,
+ * or after max_sweeps sweeps).  Each sweep is hooi_sweep; the stream is synchronised once per
+ * sweep to read the fit.
+ *   U, G        as for hooi_sweep
+ *   max_sweeps  >= 1
+ *   tol         >= 0 (0: run max_sweeps sweeps unless the fit repeats exactly)
+ *   fits_host   host double[max_sweeps] or NULL: the fit after each sweep
+ *   sweeps_done host int or NULL: the number of sweeps run
+ */
+int hooi_run(tk_ctx* ctx, double* const* U, double* G, int max_sweeps, double tol, double* fits_host,
+             int* sweeps_done, void* stream);
+
+/*
  * reconstruct - the Tucker model at sampled coordinates (paper Sec. III, the model
  * X ~ G x_1 U_1 ... x_N U_N):  out[p] = sum_r G[r] prod_k U_k(i_k(p), r_k), in FP64.
  *   G       device double[prod R_k] C-order

@@ -22,7 +22,7 @@ DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
 _STATUS = {1: "TK_ERR_ARG", 2: "TK_ERR_RANGE", 3: "TK_ERR_OOM", 4: "TK_ERR_HIP", 5: "TK_ERR_UNSUPPORTED"}
 
 EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "svd_update", "core_fit",
-           "hooi_sweep", "reconstruct", "ttmc_adjoint", "tucker_profile", "tucker_profile_read", "tucker_free",
+           "hooi_sweep", "hooi_run", "reconstruct", "ttmc_adjoint", "tucker_profile", "tucker_profile_read", "tucker_free",
            "tucker_last_error")
 
 
@@ -53,6 +53,7 @@ def load_library(path: str = LIB_PATH):
     lib.svd_update.argtypes = [P, I, P, P, P]
     lib.core_fit.argtypes = [P, P, P, P, P, P]
     lib.hooi_sweep.argtypes = [P, P, P, P, P, P]
+    lib.hooi_run.argtypes = [P, P, P, I, ctypes.c_double, P, P, P]
     lib.reconstruct.argtypes = [P, P, P, I64, P, P, P]
     lib.ttmc_adjoint.argtypes = [P, I, P, P, P, P, P, P]
     lib.tucker_profile.argtypes = [P, I]
@@ -225,6 +226,18 @@ def hooi_sweep(ctx: Ctx, U, G: torch.Tensor | None = None, fit: torch.Tensor | N
                                      _dev(fit, torch.float64, "fit"),
                                      ctypes.byref(host) if sync_fit else None, _stream()))
     return G, (host.value if sync_fit else fit)
+
+
+def hooi_run(ctx: Ctx, U, max_sweeps: int, tol: float, G: torch.Tensor | None = None):
+    """Sweeps until |fit_s - fit_{s-1}| <= tol or max_sweeps; U is updated in place.  Returns
+    (G, fits) with one fit per sweep run."""
+    if G is None:
+        G = torch.empty(ctx.ranks, dtype=torch.float64, device="cuda")
+    fits = (ctypes.c_double * max_sweeps)()
+    done = ctypes.c_int()
+    _check(load_library().hooi_run(ctx.handle, _ptrs(U, ctx.order), _dev(G, torch.float64, "G"), int(max_sweeps),
+                                   float(tol), fits, ctypes.byref(done), _stream()))
+    return G, [fits[i] for i in range(done.value)]
 
 
 def reconstruct(ctx: Ctx, G: torch.Tensor, U, coords: torch.Tensor, out: torch.Tensor | None = None):

@@ -289,6 +289,25 @@ int hooi_sweep(tk_ctx* ctx, double* const* U, double* G, double* fit_dev, double
     return TK_OK;
 }
 
+int hooi_run(tk_ctx* ctx, double* const* U, double* G, int max_sweeps, double tol, double* fits_host,
+             int* sweeps_done, void* stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (max_sweeps < 1) return set_error(TK_ERR_ARG, "max_sweeps %d < 1", max_sweeps);
+    if (!(tol >= 0.0)) return set_error(TK_ERR_ARG, "tol must be >= 0");
+    if (sweeps_done) *sweeps_done = 0;
+    double prev = 0.0;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        double f = 0.0;
+        if ((st = hooi_sweep(ctx, U, G, nullptr, &f, stream))) return st;
+        if (fits_host) fits_host[sw] = f;
+        if (sweeps_done) *sweeps_done = sw + 1;
+        if (sw >= 1 && fabs(f - prev) <= tol) break;
+        prev = f;
+    }
+    return TK_OK;
+}
+
 int reconstruct(tk_ctx* ctx, const double* G, const double* const* U, int64_t m, const int32_t* coords,
                 double* out, void* stream) {
     int st = check_ctx(ctx);

@@ -325,6 +325,29 @@ def test_hooi_sweeps_f64_200cube(tk):
     assert rel_fro(G.cpu().numpy(), Go) < 1e-10
 
 
+def test_hooi_run_stopping_rule(tk):
+    """hooi_run: the sweeps are exactly those of repeated hooi_sweep calls, it stops at the first
+    sweep whose fit changed by at most tol, and the fit sequence matches the oracle's."""
+    w = synth.hooi_small_f64(1)
+    tol = 1e-4   # reached at the 9th sweep on this tensor
+    ctx = make(tk, w, "f64")
+    U = dev_list(w.U_init)
+    G, fits = tk.hooi_run(ctx, U, max_sweeps=20, tol=tol)
+    assert 2 <= len(fits) < 20
+    ctx2 = make(tk, w, "f64")
+    U2 = dev_list(w.U_init)
+    ref = [tk.hooi_sweep(ctx2, U2, sync_fit=True)[1] for _ in range(len(fits))]
+    assert fits == ref
+    for s in range(1, len(fits) - 1):
+        assert abs(fits[s] - fits[s - 1]) > tol
+    assert abs(fits[-1] - fits[-2]) <= tol
+    _, _, fo, _ = oracle.hooi(w.coords, w.vals, w.dims, w.ranks, w.U_init, len(fits))
+    np.testing.assert_allclose(fits, fo, rtol=1e-12, atol=0)
+    with pytest.raises(tk.TuckerError) as e:
+        tk.hooi_run(ctx, U, max_sweeps=0, tol=tol)
+    assert e.value.status == 1
+
+
 def test_hooi_sweeps_lowrank_small_f32(tk):
     """Order-3 low-rank + noise (the large FP32 workload's recipe at a small size): sweep fits match
     the FP64 oracle within 1e-5 relative; factors span the same subspaces."""
