@@ -161,20 +161,32 @@ def compare_precisions(args, w, tk, torch):
         U = [torch.from_numpy(u).cuda() for u in w.U_init]
         G = torch.empty(w.ranks, dtype=torch.float64, device="cuda")
         fit = torch.empty(1, dtype=torch.float64, device="cuda")
-        fits, times = [], []
+        fits, times, all_times = [], [], []
         for k in range(args.steps + 1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             tk.hooi_sweep(ctx, U, G, fit)
             torch.cuda.synchronize()
+            all_times.append(time.perf_counter() - t0)
             if k > 0:
-                times.append(time.perf_counter() - t0)
+                times.append(all_times[-1])
             fits.append(float(fit.item()))
-        res[dt] = {"sweep_ms_median": statistics.median(times) * 1e3, "fits": fits}
+        res[dt] = {"sweep_ms_median": statistics.median(times) * 1e3, "fits": fits, "_times": all_times}
         del ctx
     ref = res["f64"]["fits"]
-    for dt in ("f32", "bf16"):
-        res[dt]["fit_rel_err_vs_f64"] = max(abs(a - b) / abs(b) for a, b in zip(res[dt]["fits"], ref) if b != 0)
+    target = ref[-1]
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2}
+    for dt in ("f64", "f32", "bf16"):
+        r = res[dt]
+        if dt != "f64":
+            r["fit_rel_err_vs_f64"] = max(abs(a - b) / abs(b) for a, b in zip(r["fits"], ref) if b != 0)
+        # time to reach the FP64 path's final fit within this precision's tolerance (sweeps run
+        # back to back, warm-up sweep included)
+        hit = next((k for k, f in enumerate(r["fits"]) if target != 0 and abs(f - target) <= tol[dt] * abs(target)),
+                   None)
+        r["sweeps_to_final_fit"] = None if hit is None else hit + 1
+        r["ms_to_final_fit"] = None if hit is None else sum(r["_times"][:hit + 1]) * 1e3
+        del r["_times"]
     out = {"workload": w.name, "dims": w.dims, "ranks": w.ranks, "nnz": int(w.nnz), "sweeps": args.steps + 1,
            "qrp": "f64", "results": res}
     print(json.dumps(out), flush=True)
