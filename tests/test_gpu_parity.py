@@ -243,6 +243,7 @@ def qrp_case(tk, dtype, dims, ranks, mode, nnz, seed, fat_rule=True):
     ([3000, 40, 30], [12, 8, 8], 0, 20000),   # tall, Gram route (K = 64)
     ([2000, 60, 50], [16, 16, 16], 0, 30000), # tall, Gram route (K = 256)
     ([4000, 40, 40], [24, 32, 32], 0, 40000), # tall, Gram route, K = 1024, R > 16, L^T in memory
+    ([3000, 40, 40], [20, 16, 16], 0, 40000), # tall, Gram route, K = 256, 16 < R <= 32: L in LDS
     ([200, 40, 30], [8, 8, 8], 0, 5000),      # small, Gram route
     ([400, 40, 40], [34, 6, 6], 0, 8000),     # R > 32: Householder route
     ([1500, 60, 50], [8, 40, 30], 0, 30000),  # K = 1200 > 1024: Householder route
