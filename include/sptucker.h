@@ -55,6 +55,7 @@ enum tk_dtype { TK_F64 = 0, TK_F32 = 1, TK_BF16 = 2 };
 /* tucker_init flags */
 #define TK_FLAG_NO_FAT_RULE 0x1u     /* factor a fat Y_(n) directly instead of Y_(n) Y_(n)^T */
 #define TK_FLAG_SVD         0x2u     /* hooi_sweep updates each factor by svd_update (Alg. 1) */
+#define TK_FLAG_SVD_LIB     0x4u     /* svd_update: rocSOLVER dsyevd for every eigenproblem */
 
 #define TK_MAX_ORDER 8               /* 2 <= N <= TK_MAX_ORDER */
 #define TK_MAX_KCOLS 4096            /* K_n = prod_{t != n} R_t must not exceed this */
@@ -133,11 +134,25 @@ int qrp_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, int32_t* piv
  * value gives a zero column.
  *   Y     device I_n x K_n (double for TK_F64, float otherwise)
  *   U_out device double I_n x R_n
+ * The R_n leading eigenpairs come from a Chebyshev-filtered subspace iteration (order <= 1024,
+ * R_n <= 32), stopped when every residual ||A v - lambda v|| <= 2e-14 lambda_max; the call reads
+ * each outer step's residual test back (one synchronisation of the stream per step).  If it
+ * does not converge within its step limit, if the shape is outside those limits, or if the
+ * context was created with TK_FLAG_SVD_LIB, rocSOLVER's dsyevd computes all eigenpairs instead.
  * Shapes the QRP handles only by Householder (R_n > 32, or K_n > 1024 on a tall Y_(n), or a fat
- * Y_(n) with TK_FLAG_NO_FAT_RULE) return TK_ERR_UNSUPPORTED.  The eigensolver's convergence flag
- * stays on the device.  Also refreshes the context's low-precision copy of U_n.
+ * Y_(n) with TK_FLAG_NO_FAT_RULE) return TK_ERR_UNSUPPORTED.  Also refreshes the context's
+ * low-precision copy of U_n.
  */
 int svd_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, void* stream);
+
+/*
+ * tucker_svd_info - which eigensolver served the context's last svd_update (host output):
+ *   outer_steps  Rayleigh-Ritz steps the subspace iteration took after the first (0 when the
+ *                start block was already converged), or -1 when rocSOLVER's dsyevd computed the
+ *                eigenpairs (no SVD update yet, TK_FLAG_SVD_LIB, shape outside the iteration's
+ *                limits, or no convergence within its step limit)
+ */
+int tucker_svd_info(const tk_ctx* ctx, int* outer_steps);
 
 /*
  * core_fit - G_(N) = U_N^T Y_(N) (Alg. 2, the step after the mode loop) and the fit.
@@ -153,7 +168,7 @@ int core_fit(tk_ctx* ctx, const void* Y_last, const double* U_last, double* G, d
  * hooi_sweep - one sweep of Alg. 2: for n = 0..N-1, TTMc with the current factors then
  * U_n <- QRP(Y_(n), R_n) (modes updated in order, each using the factors already refreshed in this
  * sweep); then the core and the fit.  A context created with TK_FLAG_SVD updates the factors with
- * svd_update instead (Alg. 1).
+ * svd_update instead (Alg. 1), which synchronises the stream a few times per mode.
  *   U        host array of N device pointers to double I_k x R_k, read and overwritten
  *   G        device double[prod R_k] (C-order), overwritten
  *   fit_dev  device double scalar or NULL

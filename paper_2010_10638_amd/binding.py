@@ -18,10 +18,12 @@ TK_OK, TK_ERR_ARG, TK_ERR_RANGE, TK_ERR_OOM, TK_ERR_HIP, TK_ERR_UNSUPPORTED = ra
 TK_F64, TK_F32, TK_BF16 = 0, 1, 2
 TK_FLAG_NO_FAT_RULE = 0x1
 TK_FLAG_SVD = 0x2
+TK_FLAG_SVD_LIB = 0x4
 DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
 _STATUS = {1: "TK_ERR_ARG", 2: "TK_ERR_RANGE", 3: "TK_ERR_OOM", 4: "TK_ERR_HIP", 5: "TK_ERR_UNSUPPORTED"}
 
-EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "svd_update", "core_fit",
+EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "svd_update",
+           "tucker_svd_info", "core_fit",
            "hooi_sweep", "hooi_run", "reconstruct", "ttmc_adjoint", "tucker_profile", "tucker_profile_read", "tucker_free",
            "tucker_last_error")
 
@@ -51,6 +53,7 @@ def load_library(path: str = LIB_PATH):
     lib.ttmc_mode.argtypes = [P, I, P, P, P]
     lib.qrp_update.argtypes = [P, I, P, P, P, P]
     lib.svd_update.argtypes = [P, I, P, P, P]
+    lib.tucker_svd_info.argtypes = [P, P]
     lib.core_fit.argtypes = [P, P, P, P, P, P]
     lib.hooi_sweep.argtypes = [P, P, P, P, P, P]
     lib.hooi_run.argtypes = [P, P, P, I, ctypes.c_double, P, P, P]
@@ -126,9 +129,10 @@ class Ctx:
 
 
 def tucker_init(coords: torch.Tensor, vals: torch.Tensor, dims, ranks, dtype: str = "f32",
-                fat_rule: bool = True, svd: bool = False) -> Ctx:
+                fat_rule: bool = True, svd: bool = False, svd_lib: bool = False) -> Ctx:
     """coords: int32 [N, nnz] (0-based), vals: float64 [nnz], both on the GPU.  svd: hooi_sweep
-    updates the factors by svd_update instead of qrp_update."""
+    updates the factors by svd_update instead of qrp_update.  svd_lib: svd_update uses rocSOLVER's
+    dsyevd for every eigenproblem instead of the library's own subspace iteration."""
     lib = load_library()
     N = len(dims)
     if coords.dim() != 2 or coords.shape[0] != N:
@@ -139,7 +143,8 @@ def tucker_init(coords: torch.Tensor, vals: torch.Tensor, dims, ranks, dtype: st
     d = (ctypes.c_int64 * N)(*[int(x) for x in dims])
     r = (ctypes.c_int32 * N)(*[int(x) for x in ranks])
     h = ctypes.c_void_p()
-    flags = (0 if fat_rule else TK_FLAG_NO_FAT_RULE) | (TK_FLAG_SVD if svd else 0)
+    flags = ((0 if fat_rule else TK_FLAG_NO_FAT_RULE) | (TK_FLAG_SVD if svd else 0)
+             | (TK_FLAG_SVD_LIB if svd_lib else 0))
     cp = _dev(coords, torch.int32, "coords") if nnz else None
     vp = _dev(vals, torch.float64, "vals") if nnz else None
     _check(lib.tucker_init(ctypes.byref(h), N, d, r, nnz, cp, vp, DTYPES[dtype], flags, _stream()))
@@ -199,6 +204,14 @@ def svd_update(ctx: Ctx, mode: int, Y: torch.Tensor, U_out: torch.Tensor | None 
     _check(load_library().svd_update(ctx.handle, mode, _dev(Y, ctx.ytype, "Y"),
                                      _dev(U_out, torch.float64, "U_out"), _stream()))
     return U_out
+
+
+def svd_info(ctx: Ctx) -> int:
+    """Rayleigh-Ritz steps the library's subspace iteration took in the last svd_update (beyond the
+    first), or -1 when rocSOLVER's dsyevd served it."""
+    v = ctypes.c_int(0)
+    _check(load_library().tucker_svd_info(ctx.handle, ctypes.byref(v)))
+    return v.value
 
 
 def core_fit(ctx: Ctx, Y_last: torch.Tensor, U_last: torch.Tensor, G: torch.Tensor | None = None,

@@ -107,7 +107,8 @@ int tucker_init(tk_ctx** out, int order, const int64_t* dims, const int32_t* ran
     if (nnz < 0) return set_error(TK_ERR_ARG, "negative nnz");
     if (nnz >= (int64_t)1 << 31) return set_error(TK_ERR_UNSUPPORTED, "nnz %lld >= 2^31", (long long)nnz);
     if (nnz > 0 && (!coords || !vals)) return set_error(TK_ERR_ARG, "coords/vals is null");
-    if (flags & ~(TK_FLAG_NO_FAT_RULE | TK_FLAG_SVD)) return set_error(TK_ERR_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(TK_FLAG_NO_FAT_RULE | TK_FLAG_SVD | TK_FLAG_SVD_LIB))
+        return set_error(TK_ERR_ARG, "unknown flags 0x%x", flags);
     double log2prod = 0.0;
     for (int t = 0; t < order; ++t) {
         if (dims[t] < 1) return set_error(TK_ERR_ARG, "dims[%d] = %lld < 1", t, (long long)dims[t]);
@@ -239,6 +240,14 @@ int svd_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, void* stream
     st = svd_run(ctx, mode, Y, U_out, s);
     ctx->last_stream = s;
     return st;
+}
+
+int tucker_svd_info(const tk_ctx* ctx, int* outer_steps) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!outer_steps) return set_error(TK_ERR_ARG, "outer_steps is null");
+    *outer_steps = ctx->eig_outer;
+    return TK_OK;
 }
 
 int core_fit(tk_ctx* ctx, const void* Y_last, const double* U_last, double* G, double* fit, void* stream) {

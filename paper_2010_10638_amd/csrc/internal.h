@@ -126,6 +126,8 @@ struct tk_ctx {
     double* svd_d = nullptr;         // eigenvalues, TK_MAX_KCOLS
     double* svd_e = nullptr;         // off-diagonal workspace, TK_MAX_KCOLS
     int32_t* svd_info = nullptr;
+    double* eig_ws = nullptr;        // one-workgroup eigensolver: blocks, eigenpairs, status
+    int eig_outer = -1;              // its outer steps in the last SVD update (-1: library solver)
     hipStream_t last_stream = nullptr;
     int device = 0;
     int ncu = 0;                     // compute units of the device

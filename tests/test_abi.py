@@ -56,7 +56,7 @@ def _init(lib, order=3, dims=(5, 6, 7), ranks=(2, 2, 2), nnz=0, dtype=1, flags=0
     (dict(nnz=1 << 31), 5),
     (dict(nnz=10), 1),                                   # coords/vals null
     (dict(flags=0x80), 1),
-    (dict(flags=0x4), 1),
+    (dict(flags=0x8), 1),
     (dict(ranks=(6, 2, 2)), 1),                          # R_1 > I_1
     (dict(dims=(5, 0, 7)), 1),
     (dict(dims=(2000,) * 3, ranks=(65, 65, 65)), 5),     # K_n = 4225 > 4096
@@ -74,6 +74,7 @@ def test_null_context_is_rejected(lib):
     assert lib.hooi_sweep(None, None, None, None, None, None) == 1
     assert lib.reconstruct(None, None, None, 0, None, None, None) == 1
     assert lib.svd_update(None, 0, None, None, None) == 1
+    assert lib.tucker_svd_info(None, None) == 1
     assert lib.hooi_run(None, None, None, 1, ctypes.c_double(0.0), None, None, None) == 1
     lib.tucker_free(None)
 
