@@ -151,18 +151,11 @@ __device__ void eig_orth(double* Y, int n, int b, int ld, OrthLds& L) {
 // m = b + 1 even) by one wave, accumulated into L.S, until the off-diagonal sum of squares is at
 // most 1e-30 of the diagonal's.  A round-robin round holds m/2 disjoint rotations; they are
 // applied together as H <- J^T H J, each lane updating whole 2 x 2 blocks (rows of one pair,
-// columns of another) and rows of S.  The pairs being disjoint, every entry a round touches is
-// read before any is written back (in chunks, to bound the registers).
+// columns of another) and S.  The pairs being disjoint, every entry a round touches is read
+// before any is written back (in chunks, to bound the registers).
 constexpr int kJacBlk = (kEigMaxB / 2) * (kEigMaxB / 2) / 64 + 1;   // 2 x 2 blocks per lane
 constexpr int kJacChunk = 4;                                        // blocks in flight
-constexpr int kJacPairChunk = 8;                                    // S pairs in flight
-
-__device__ inline double eig_readlane(double v, int k) {
-    const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), k);
-    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), k);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
+constexpr int kJacPairChunk = 8;                                    // S rows in flight
 
 __device__ void eig_jacobi(EigLds& L, int b) {
     const int lane = threadIdx.x & 63;
@@ -182,12 +175,14 @@ __device__ void eig_jacobi(EigLds& L, int b) {
         dia = eig_wave_sum(dia);
         if (!(off > 1e-30 * dia)) break;
         for (int rnd = 0; rnd < m - 1; ++rnd) {
-            // lane k < half: rotation of pair k, kept in registers and published in LDS
+            // lanes k and 32 + k (k < half): rotation of pair k, kept in registers; lane k also
+            // publishes it in LDS
+            const int kk = lane & 31;
             int p = 0, q = 0;
             double c = 1.0, sn = 0.0;
-            if (lane < half) {
-                p = (lane == 0) ? m - 1 : (rnd + lane) % (m - 1);
-                q = (lane == 0) ? rnd : (rnd - lane + (m - 1)) % (m - 1);
+            if (kk < half) {
+                p = (kk == 0) ? m - 1 : (rnd + kk) % (m - 1);
+                q = (kk == 0) ? rnd : (rnd - kk + (m - 1)) % (m - 1);
                 if (p > q) { const int x = p; p = q; q = x; }
                 const double hpq = L.H[p][q];
                 if (hpq != 0.0) {
@@ -196,10 +191,12 @@ __device__ void eig_jacobi(EigLds& L, int b) {
                     c = 1.0 / sqrt(1.0 + tt * tt);
                     sn = tt * c;
                 }
-                L.pp[lane] = p;
-                L.qq[lane] = q;
-                L.cs[lane] = c;
-                L.sn[lane] = sn;
+                if (lane < 32) {
+                    L.pp[lane] = p;
+                    L.qq[lane] = q;
+                    L.cs[lane] = c;
+                    L.sn[lane] = sn;
+                }
             }
             eig_wave_sync();
             for (int u0 = 0; u0 < kJacBlk; u0 += kJacChunk) {
@@ -238,27 +235,28 @@ __device__ void eig_jacobi(EigLds& L, int b) {
                     L.H[bq1[u]][bq2[u]] = s2 * c1r + c2 * d1;
                 }
             }
-            // S <- S J: lane j updates row j; the pair's rotation is read from lane k's registers
-            for (int k0 = 0; k0 < half; k0 += kJacPairChunk) {
-                int pk[kJacPairChunk], qk[kJacPairChunk];
-                double ck[kJacPairChunk], sk[kJacPairChunk], sp[kJacPairChunk], sq[kJacPairChunk];
+            // S <- S J: lanes k and 32 + k apply pair k's rotation to columns p, q of rows
+            // [0, 24) and [24, 48) respectively
+            if (kk < half) {
+                const int j0 = (lane >> 5) * (kEigMaxB / 2);
 #pragma unroll
-                for (int u = 0; u < kJacPairChunk; ++u) {
-                    const int k = min(k0 + u, half - 1);
-                    pk[u] = __builtin_amdgcn_readlane(p, k);
-                    qk[u] = __builtin_amdgcn_readlane(q, k);
-                    ck[u] = eig_readlane(c, k);
-                    sk[u] = eig_readlane(sn, k);
-                    if (lane < m && k0 + u < half) {
-                        sp[u] = L.S[lane][pk[u]];
-                        sq[u] = L.S[lane][qk[u]];
+                for (int i0 = 0; i0 < kEigMaxB / 2; i0 += kJacPairChunk) {
+                    double sp[kJacPairChunk], sq[kJacPairChunk];
+#pragma unroll
+                    for (int u = 0; u < kJacPairChunk; ++u) {
+                        const int j = j0 + i0 + u;
+                        if (j < m) {
+                            sp[u] = L.S[j][p];
+                            sq[u] = L.S[j][q];
+                        }
                     }
-                }
 #pragma unroll
-                for (int u = 0; u < kJacPairChunk; ++u) {
-                    if (lane < m && k0 + u < half) {
-                        L.S[lane][pk[u]] = ck[u] * sp[u] - sk[u] * sq[u];
-                        L.S[lane][qk[u]] = sk[u] * sp[u] + ck[u] * sq[u];
+                    for (int u = 0; u < kJacPairChunk; ++u) {
+                        const int j = j0 + i0 + u;
+                        if (j < m) {
+                            L.S[j][p] = c * sp[u] - sn * sq[u];
+                            L.S[j][q] = sn * sp[u] + c * sq[u];
+                        }
                     }
                 }
             }
