@@ -42,7 +42,7 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 // filter's growth rate for theta_r, capped so that p_d(theta_0) / p_d(theta_{R-1}) <= 1e12 (a
 // larger spread swamps the lower Ritz directions in rounding error), and at kEigMaxDeg.
 constexpr int kEigT = 1024;          // threads of the one-workgroup steps
-constexpr int kRrT = 512;            // threads of the Rayleigh-Ritz step (256 VGPRs for its Jacobi wave)
+constexpr int kRrT = 512;            // threads of the Rayleigh-Ritz step
 constexpr int kEigMaxB = 48;         // block size limit (R <= 32)
 constexpr int kEigMaxN = 1024;
 constexpr int kEigKT = 32;           // rows of a staged LDS tile
@@ -72,12 +72,6 @@ struct EigLds {
     int ctl_state, ctl_deg;             // state: 1 converged, 0 filter, 2 plain power step
 };
 
-
-__device__ inline void eig_wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ inline double eig_wave_sum(double v) {
 #pragma unroll
@@ -148,42 +142,45 @@ __device__ void eig_orth(double* Y, int n, int b, int ld, OrthLds& L) {
 }
 
 // Cyclic Jacobi on L.H (b x b, symmetric; for odd b a zero row and column b make the order
-// m = b + 1 even) by one wave, accumulated into L.S, until the off-diagonal sum of squares is at
-// most 1e-30 of the diagonal's.  A round-robin round holds m/2 disjoint rotations; they are
-// applied together as H <- J^T H J, each lane updating whole 2 x 2 blocks (rows of one pair,
-// columns of another) and S.  The pairs being disjoint, every entry a round touches is read
-// before any is written back (in chunks, to bound the registers).
-constexpr int kJacBlk = (kEigMaxB / 2) * (kEigMaxB / 2) / 64 + 1;   // 2 x 2 blocks per lane
-constexpr int kJacChunk = 4;                                        // blocks in flight
-constexpr int kJacPairChunk = 8;                                    // S rows in flight
-
+// m = b + 1 even) by the whole workgroup, accumulated into L.S, until the off-diagonal sum of
+// squares is at most 1e-30 of the diagonal's.  A round-robin round holds m/2 disjoint rotations:
+// threads k < m/2 compute them, then all threads apply them together as H <- J^T H J (a thread per
+// 2 x 2 block: rows of one pair, columns of another) and S <- S J (a thread per row and pair); two
+// barriers per round.
 __device__ void eig_jacobi(EigLds& L, int b) {
-    const int lane = threadIdx.x & 63;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int m = b + (b & 1);
     const int half = m / 2;
-    const int nblk = half * half;
-    for (int e = lane; e < m * m; e += 64) L.S[e / m][e % m] = (e / m == e % m) ? 1.0 : 0.0;
-    eig_wave_sync();
+    for (int e = t; e < m * m; e += kRrT) L.S[e / m][e % m] = (e / m == e % m) ? 1.0 : 0.0;
+    __syncthreads();
     for (int sweep = 0; sweep < 30; ++sweep) {
         double off = 0.0, dia = 0.0;
-        for (int e = lane; e < b * b; e += 64) {
+        for (int e = t; e < b * b; e += kRrT) {
             const double v = L.H[e / b][e % b];
             if (e / b == e % b) dia += v * v;
             else off += v * v;
         }
         off = eig_wave_sum(off);
         dia = eig_wave_sum(dia);
+        if (lane == 0) {
+            L.o.red[w][0] = off;
+            L.o.red[w][1] = dia;
+        }
+        __syncthreads();
+        off = 0.0;
+        dia = 0.0;
+        for (int q = 0; q < kRrT / 64; ++q) {
+            off += L.o.red[q][0];
+            dia += L.o.red[q][1];
+        }
+        __syncthreads();
         if (!(off > 1e-30 * dia)) break;
         for (int rnd = 0; rnd < m - 1; ++rnd) {
-            // lanes k and 32 + k (k < half): rotation of pair k, kept in registers; lane k also
-            // publishes it in LDS
-            const int kk = lane & 31;
-            int p = 0, q = 0;
-            double c = 1.0, sn = 0.0;
-            if (kk < half) {
-                p = (kk == 0) ? m - 1 : (rnd + kk) % (m - 1);
-                q = (kk == 0) ? rnd : (rnd - kk + (m - 1)) % (m - 1);
+            if (t < half) {
+                int p = (t == 0) ? m - 1 : (rnd + t) % (m - 1);
+                int q = (t == 0) ? rnd : (rnd - t + (m - 1)) % (m - 1);
                 if (p > q) { const int x = p; p = q; q = x; }
+                double c = 1.0, sn = 0.0;
                 const double hpq = L.H[p][q];
                 if (hpq != 0.0) {
                     const double tau = (L.H[q][q] - L.H[p][p]) / (2.0 * hpq);
@@ -191,76 +188,33 @@ __device__ void eig_jacobi(EigLds& L, int b) {
                     c = 1.0 / sqrt(1.0 + tt * tt);
                     sn = tt * c;
                 }
-                if (lane < 32) {
-                    L.pp[lane] = p;
-                    L.qq[lane] = q;
-                    L.cs[lane] = c;
-                    L.sn[lane] = sn;
-                }
+                L.pp[t] = p;
+                L.qq[t] = q;
+                L.cs[t] = c;
+                L.sn[t] = sn;
             }
-            eig_wave_sync();
-            for (int u0 = 0; u0 < kJacBlk; u0 += kJacChunk) {
-                if (lane + 64 * u0 >= nblk) break;
-                int bp1[kJacChunk], bq1[kJacChunk], bp2[kJacChunk], bq2[kJacChunk];
-                double v[kJacChunk][4], r[kJacChunk][4];
-#pragma unroll
-                for (int u = 0; u < kJacChunk; ++u) {
-                    const int e = lane + 64 * (u0 + u);
-                    const bool ok = e < nblk;
-                    const int k1 = ok ? e / half : 0, k2 = ok ? e % half : 0;
-                    bp1[u] = ok ? L.pp[k1] : -1;
-                    bq1[u] = L.qq[k1];
-                    bp2[u] = L.pp[k2];
-                    bq2[u] = L.qq[k2];
-                    r[u][0] = L.cs[k1];
-                    r[u][1] = L.sn[k1];
-                    r[u][2] = L.cs[k2];
-                    r[u][3] = L.sn[k2];
-                    if (ok) {
-                        v[u][0] = L.H[bp1[u]][bp2[u]];
-                        v[u][1] = L.H[bp1[u]][bq2[u]];
-                        v[u][2] = L.H[bq1[u]][bp2[u]];
-                        v[u][3] = L.H[bq1[u]][bq2[u]];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kJacChunk; ++u) {
-                    if (bp1[u] < 0) continue;
-                    const double c1 = r[u][0], s1 = r[u][1], c2 = r[u][2], s2 = r[u][3];
-                    const double a1 = c1 * v[u][0] - s1 * v[u][2], b1 = c1 * v[u][1] - s1 * v[u][3];   // J^T
-                    const double c1r = s1 * v[u][0] + c1 * v[u][2], d1 = s1 * v[u][1] + c1 * v[u][3];
-                    L.H[bp1[u]][bp2[u]] = c2 * a1 - s2 * b1;                                           // J
-                    L.H[bp1[u]][bq2[u]] = s2 * a1 + c2 * b1;
-                    L.H[bq1[u]][bp2[u]] = c2 * c1r - s2 * d1;
-                    L.H[bq1[u]][bq2[u]] = s2 * c1r + c2 * d1;
-                }
+            __syncthreads();
+            for (int e = t; e < half * half; e += kRrT) {
+                const int k1 = e / half, k2 = e % half;
+                const int p1 = L.pp[k1], q1 = L.qq[k1], p2 = L.pp[k2], q2 = L.qq[k2];
+                const double c1 = L.cs[k1], s1 = L.sn[k1], c2 = L.cs[k2], s2 = L.sn[k2];
+                const double a = L.H[p1][p2], bb = L.H[p1][q2], cc = L.H[q1][p2], d = L.H[q1][q2];
+                const double a1 = c1 * a - s1 * cc, b1 = c1 * bb - s1 * d;    // rows: J^T
+                const double c1r = s1 * a + c1 * cc, d1 = s1 * bb + c1 * d;
+                L.H[p1][p2] = c2 * a1 - s2 * b1;                                // columns: J
+                L.H[p1][q2] = s2 * a1 + c2 * b1;
+                L.H[q1][p2] = c2 * c1r - s2 * d1;
+                L.H[q1][q2] = s2 * c1r + c2 * d1;
             }
-            // S <- S J: lanes k and 32 + k apply pair k's rotation to columns p, q of rows
-            // [0, 24) and [24, 48) respectively
-            if (kk < half) {
-                const int j0 = (lane >> 5) * (kEigMaxB / 2);
-#pragma unroll
-                for (int i0 = 0; i0 < kEigMaxB / 2; i0 += kJacPairChunk) {
-                    double sp[kJacPairChunk], sq[kJacPairChunk];
-#pragma unroll
-                    for (int u = 0; u < kJacPairChunk; ++u) {
-                        const int j = j0 + i0 + u;
-                        if (j < m) {
-                            sp[u] = L.S[j][p];
-                            sq[u] = L.S[j][q];
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < kJacPairChunk; ++u) {
-                        const int j = j0 + i0 + u;
-                        if (j < m) {
-                            L.S[j][p] = c * sp[u] - sn * sq[u];
-                            L.S[j][q] = sn * sp[u] + c * sq[u];
-                        }
-                    }
-                }
+            for (int e = t; e < half * m; e += kRrT) {
+                const int k = e / m, j = e % m;
+                const int p = L.pp[k], q = L.qq[k];
+                const double c = L.cs[k], sn = L.sn[k];
+                const double sp = L.S[j][p], sq = L.S[j][q];
+                L.S[j][p] = c * sp - sn * sq;
+                L.S[j][q] = sn * sp + c * sq;
             }
-            eig_wave_sync();
+            __syncthreads();
         }
     }
 }
@@ -312,7 +266,7 @@ __device__ void eig_rr(const double* Z, const double* P, double* X, double* AX, 
         L.H[t][b] = 0.0;
     }
     __syncthreads();
-    if (t < 64) eig_jacobi(L, b);
+    eig_jacobi(L, b);
     __syncthreads();
     if (t < b) {
         const double v = L.H[t][t];
