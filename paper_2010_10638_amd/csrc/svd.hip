@@ -476,23 +476,46 @@ __global__ __launch_bounds__(kRrT) void k_eig_rr(const double* Z, double* P, dou
 // j = n-1-r (ascending, all n of them); eigenvector j at V + j n.
 __device__ inline int64_t eig_index(int r, int64_t n, int desc) { return desc ? r : n - 1 - r; }
 
-// Tall case: U[i][r] = (sum_c Y[i][c] v_r[c]) / sqrt(lambda_r).  One thread per output entry
-// (the lanes of a row read the same Y entries; the R eigenvectors stay in cache), c ascending.
-template <typename YT>
-__global__ __launch_bounds__(256) void k_svd_left(const YT* __restrict__ Y, int64_t I, int K,
+// Tall case: U[i][r] = (sum_c Y[i][c] v_r[c]) / sqrt(lambda_r), c ascending.  A thread per row
+// (RM >= R accumulators in registers); the eigenvectors are staged through LDS 64 entries at a
+// time.
+template <typename YT, int RM>
+__global__ __launch_bounds__(128) void k_svd_left(const YT* __restrict__ Y, int64_t I, int K,
                                                   const double* __restrict__ V, const double* __restrict__ D,
                                                   int desc, int R, double* __restrict__ U) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= I * R) return;
-    const int64_t i = e / R;
-    const int r = (int)(e % R);
-    const YT* y = Y + i * K;
-    const int64_t j = eig_index(r, K, desc);
-    const double* v = V + j * K;
-    double acc = 0.0;
-    for (int c = 0; c < K; ++c) acc += (double)y[c] * v[c];
-    const double lam = D[j];
-    U[e] = (lam > 0.0) ? acc / sqrt(lam) : 0.0;
+    __shared__ double vs[64][RM + 1];
+    __shared__ double sq[RM];
+    const int t = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 128 + t;
+    if (t < R) {
+        const double lam = D[eig_index(t, K, desc)];
+        sq[t] = (lam > 0.0) ? sqrt(lam) : 0.0;
+    }
+    double acc[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) acc[r] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += 64) {
+        __syncthreads();
+        for (int e = t; e < 64 * RM; e += 128) {
+            const int c = e / RM, r = e % RM;
+            vs[c][r] = (r < R && k0 + c < K) ? V[eig_index(r, K, desc) * K + k0 + c] : 0.0;
+        }
+        __syncthreads();
+        if (i < I) {
+            const YT* y = Y + i * K + k0;
+            const int kc = min(64, K - k0);
+#pragma unroll 8
+            for (int c = 0; c < kc; ++c) {
+                const double yv = (double)y[c];
+#pragma unroll
+                for (int r = 0; r < RM; ++r) acc[r] = fma(yv, vs[c][r], acc[r]);
+            }
+        }
+    }
+    if (i >= I) return;
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+        if (r < R) U[i * R + r] = (sq[r] > 0.0) ? acc[r] / sq[r] : 0.0;
 }
 
 // Fat case: U[i][r] = entry i of the r-th leading eigenvector of Y Y^T.
@@ -504,7 +527,8 @@ __global__ void k_svd_fat(const double* __restrict__ V, int64_t I, int desc, int
     U[e] = V[eig_index(r, I, desc) * I + i];
 }
 
-// One workgroup per column: the entry of largest magnitude (first one on ties) made positive.
+// Sign convention: in each column the entry of largest magnitude (the first one on ties) made
+// positive.  One workgroup per column.
 __global__ __launch_bounds__(256) void k_svd_sign(double* __restrict__ U, int64_t I, int R) {
     __shared__ double s_v[256];
     __shared__ int64_t s_i[256];
@@ -536,7 +560,9 @@ int left_typed(const tk_ctx* ctx, int mode, const YT* Y, const double* V, const 
                double* U, hipStream_t s) {
     const int64_t I = ctx->dims[mode];
     const int K = (int)ctx->mode[mode].K, R = ctx->ranks[mode];
-    k_svd_left<YT><<<cdiv(I * R, 256), 256, 0, s>>>(Y, I, K, V, D, desc, R, U);
+    if (R <= 8) k_svd_left<YT, 8><<<cdiv(I, 128), 128, 0, s>>>(Y, I, K, V, D, desc, R, U);
+    else if (R <= 16) k_svd_left<YT, 16><<<cdiv(I, 128), 128, 0, s>>>(Y, I, K, V, D, desc, R, U);
+    else k_svd_left<YT, 32><<<cdiv(I, 128), 128, 0, s>>>(Y, I, K, V, D, desc, R, U);
     TK_LAUNCH_CHECK("k_svd_left");
     return TK_OK;
 }

@@ -104,6 +104,19 @@ def test_svd_hooi_sweeps_f64(tk, solver):
     assert abs(np.linalg.norm(G.cpu().numpy()) - np.linalg.norm(Go)) <= 1e-10 * np.linalg.norm(Go)
 
 
+def test_svd_update_fat_wide_rank(tk):
+    """Fat Y_(n) (K = 64 > I = 40) with R = 34: past the subspace iteration's R <= 32, so dsyevd
+    serves it (tucker_svd_info = -1), and the signs are fixed one column per workgroup."""
+    dims, ranks = [40, 8, 8], [34, 8, 8]
+    w = synth.small_uniform(77, dims, ranks, 2000)
+    ctx = make(tk, w, "f64")
+    Yo = oracle.ttmc(w.coords, w.vals, dims, ranks, 0, w.U_init)
+    Yd = torch.from_numpy(Yo).cuda().contiguous()
+    U = tk.svd_update(ctx, 0, Yd).cpu().numpy()
+    assert tk.svd_info(ctx) == -1
+    np.testing.assert_allclose(U, signed(oracle.svd_factor(Yo, 34)), atol=1e-9)
+
+
 def test_svd_unsupported_shape(tk):
     """R_n > 32 on a tall Y has no Gram route: refused with TK_ERR_UNSUPPORTED."""
     w = synth.small_uniform(5, [400, 40, 40], [34, 6, 6], 8000)
