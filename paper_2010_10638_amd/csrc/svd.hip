@@ -67,7 +67,6 @@ struct EigLds {
     double cs[kEigMaxB / 2], sn[kEigMaxB / 2];
     int pp[kEigMaxB / 2], qq[kEigMaxB / 2];
     int perm[kEigMaxB];                 // Jacobi index of the r-th largest Ritz value
-    int sel[kEigMaxB];
     double ctl_c, ctl_e, ctl_tl;
     int ctl_state, ctl_deg;             // state: 1 converged, 0 filter, 2 plain power step
 };

@@ -53,6 +53,8 @@ def check_solver(tk, ctx, solver):
     ([900, 30, 40], [24, 16, 20], 0, 30000),       # tall, K = 320, R = 24
     ([20, 30, 25, 40], [5, 4, 4, 4], 0, 6000),     # fat (K = 64 > 20): eigenvectors of Y Y^T
     ([3000, 32, 32], [16, 32, 32], 0, 20000),      # K = 1024: block orthonormalised in global memory
+    ([300, 3, 3], [8, 3, 3], 0, 2000),             # K = 9: block = whole space, odd (padded Jacobi)
+    ([500, 20, 20], [1, 4, 4], 0, 5000),           # R = 1
 ])
 def test_svd_update_parity(tk, dtype, case, solver):
     dims, ranks, mode, nnz = case
