@@ -275,8 +275,8 @@ def main():
         print(summarize_pmc(*args.summarize_pmc, kernel="k_ttmc3_lds<float>"))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the TTMc and QRP would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the TTMc would "
+              "shard by output rows, the QRP by an all-reduce of the Gram matrix).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -42,7 +42,7 @@ enum tk_status {
     TK_ERR_RANGE = 2,        /* a coordinate lies outside [0, I_k) */
     TK_ERR_OOM = 3,          /* device allocation failed */
     TK_ERR_HIP = 4,          /* a HIP runtime call or kernel failed */
-    TK_ERR_UNSUPPORTED = 5   /* valid input outside this build's limits (see TK_MAX_*) */
+    TK_ERR_UNSUPPORTED = 5   /* valid input outside the library's compiled limits (TK_MAX_*) */
 };
 
 /* Arithmetic of the TTMc (the QRP, core and fit always run in FP64):
