@@ -123,6 +123,8 @@ TTMC_CASES = [
     ([20, 18, 16, 14], [20, 3, 4, 5], 8000),   # inner rank > 16 for some modes: generic path
     ([300, 250], [6, 6], 4000),                # order 2 (SpMM); R_1 <= K_1 = R_2 forces equal ranks
     ([50, 40, 30], [20, 3, 17], 4000),         # R > 16: generic path for order 3
+    ([6, 5, 5, 4, 4, 3], [2, 2, 2, 2, 2, 2], 1500),              # order 6: generic path
+    ([4, 4, 4, 3, 3, 3, 3, 3], [2, 2, 2, 2, 2, 2, 2, 2], 3000),  # order 8 (the compiled maximum)
 ]
 
 
