@@ -90,13 +90,14 @@ __device__ double eig_block_sum(double v, OrthLds& L) {
 }
 
 // Columns 0..b-1 of Y (n rows, row stride ld) made orthonormal in place: classical Gram-Schmidt,
-// twice per column; a column left with under 1e-8 of its norm is replaced by a unit vector and
-// redone.  Y is in LDS or global memory.
+// a second pass only when the first removed more than half of the column's squared norm (Kahan
+// and Parlett's "twice is enough"); a column left with under 1e-8 of its norm is replaced by a
+// unit vector and redone.  Y is in LDS or global memory.
 __device__ void eig_orth(double* Y, int n, int b, int ld, OrthLds& L) {
     const int t = threadIdx.x, k = t & 63, g = t >> 6;
     for (int j = 0; j < b; ++j) {
         for (int attempt = 0; attempt < 4; ++attempt) {
-            double before = 0.0;
+            double before = 0.0, nn = 0.0;
             for (int pass = 0; pass < 2; ++pass) {
                 double s = 0.0;
                 if (k <= j) {
@@ -120,13 +121,14 @@ __device__ void eig_orth(double* Y, int n, int b, int ld, OrthLds& L) {
                     Y[(int64_t)i * ld + j] = v;
                 }
                 __syncthreads();
+                double sq = 0.0;
+                for (int i = t; i < n; i += kEigT) {
+                    const double v = Y[(int64_t)i * ld + j];
+                    sq = fma(v, v, sq);
+                }
+                nn = eig_block_sum(sq, L);
+                if (pass == 0 && nn >= 0.5 * before) break;
             }
-            double s = 0.0;
-            for (int i = t; i < n; i += kEigT) {
-                const double v = Y[(int64_t)i * ld + j];
-                s = fma(v, v, s);
-            }
-            const double nn = eig_block_sum(s, L);
             if (nn > 1e-16 * before && nn > 0.0) {
                 const double inv = 1.0 / sqrt(nn);
                 for (int i = t; i < n; i += kEigT) Y[(int64_t)i * ld + j] *= inv;
