@@ -5,13 +5,16 @@
 //   xhat_p = sum_r G[r] prod_k U_k(i_k, r_k),   e_p = xhat_p - x_p,   L = sum_p e_p^2 / (2 |Omega|)
 //   dL/dU_n   = TTMc_n(E) G_(n)^T / |Omega|        (TTMc_n(E) = E_(n) kron_{k != n} U_k, I_n x K_n)
 //   dL/dG_(N) = U_N^T TTMc_N(E) / |Omega|
-// where E is the sparse tensor of residuals on the pattern of X.  Per mode n the residuals are
-// computed on mode n's own sorted stream: with W_n = U_n G_(n) (I_n x K_n, dense), the model value
-// of an entry is the dot product of row i_n of W_n with the entry's Kronecker row, so no
-// permutation between the modes' orders is needed.  The residual values then replace the tensor
-// values in the ordinary TTMc kernels (the adjoint reuses the forward kernels unchanged), and two
-// small dense products give the gradients.  All sums have a fixed order: results are
-// deterministic.
+// where E is the sparse tensor of residuals on the pattern of X.  The residuals are computed once,
+// on mode 0's sorted stream: with W_0 = U_0 G_(0) (I_0 x K_0, dense), the model value of an entry
+// is the dot product of row i_0 of W_0 with the entry's Kronecker row.  Every other mode gathers
+// them into its own stream order through a position map built at the first call (both streams
+// sorted by the same lexicographic coordinate key: the r-th entries are the same nonzero).  The
+// residual values then replace the tensor values in the ordinary TTMc kernels (the adjoint reuses
+// the forward kernels unchanged), and two small dense products give the gradients.  All sums have
+// a fixed order: results are deterministic.
+#include <hipcub/hipcub.hpp>
+
 #include <type_traits>
 
 #include "internal.h"
@@ -331,6 +334,55 @@ __global__ void k_fill(AT* __restrict__ p, int64_t n) {
     if (e < n) p[e] = (AT)0;
 }
 
+// Lexicographic key (i_0, ..., i_{N-1}) of every padded position of mode m (padding: `pad`,
+// which sorts after every real key), and the position itself as the sort value.
+struct LexSpec {
+    int64_t dims[kMaxOrder];
+    int others[kMaxOrder - 1];
+    int N, m;
+};
+
+__global__ void k_lex_keys(LexSpec ls, const int32_t* __restrict__ rowid, const int32_t* __restrict__ rows,
+                           const int32_t* __restrict__ ptr, const int32_t* __restrict__ pptr,
+                           const int32_t* __restrict__ idx, int64_t P, uint64_t pad, uint64_t* __restrict__ keys,
+                           int32_t* __restrict__ pos) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    const int s = rowid[q];
+    pos[q] = (int32_t)q;
+    if (q - pptr[s] >= (int64_t)ptr[s + 1] - ptr[s]) {
+        keys[q] = pad;
+        return;
+    }
+    int64_t c[kMaxOrder];
+    c[ls.m] = rows[s];
+    for (int j = 0; j < ls.N - 1; ++j) c[ls.others[j]] = idx[(int64_t)j * P + q] & kIndexMask;
+    uint64_t key = 0;
+    for (int t = 0; t < ls.N; ++t) key = key * (uint64_t)ls.dims[t] + (uint64_t)c[t];
+    keys[q] = key;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
+// map[pos_n[r]] = pos_0[r] for the D real entries (the first D of both sorted orders)
+__global__ void k_map(const int32_t* __restrict__ pos0, const int32_t* __restrict__ posn, int64_t D,
+                      int32_t* __restrict__ map) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < D) map[posn[r]] = pos0[r];
+}
+
+// residuals of mode 0's stream into mode n's order (zero on padding)
+template <typename AT>
+__global__ void k_permute(const int32_t* __restrict__ map, int64_t P, const AT* __restrict__ e0, AT* __restrict__ en) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    const int32_t src = map[q];
+    en[q] = (src >= 0) ? e0[src] : (AT)0;
+}
+
 void gg_plan(int64_t I, int64_t K, int R, int& nsplit, int64_t& slab) {
     const int64_t cblocks = ((K + 63) / 64) * ((R + 63) / 64);
     nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(cblocks, 1), (I + 127) / 128));
@@ -365,8 +417,9 @@ int ensure_ws(tk_ctx* ctx, hipStream_t s) {
         return TK_OK;
     };
     int st;
-    if ((st = alloc(&w.e, (size_t)maxP * at)) || (st = alloc(&w.W, (size_t)maxIK * at)) ||
-        (st = alloc(&w.Gn, (size_t)gn * at)) || (st = alloc((void**)&w.part, (size_t)part * 8)))
+    if ((st = alloc(&w.e, (size_t)maxP * at)) || (st = alloc(&w.e2, (size_t)maxP * at)) ||
+        (st = alloc(&w.W, (size_t)maxIK * at)) || (st = alloc(&w.Gn, (size_t)gn * at)) ||
+        (st = alloc((void**)&w.part, (size_t)part * 8)))
         return st;
     for (int n = 0; n < N; ++n) {
         const ModeLayout& ml = ctx->mode[n];
@@ -375,6 +428,69 @@ int ensure_ws(tk_ctx* ctx, hipStream_t s) {
             k_rowid<<<cdiv(ml.P, 256), 256, 0, s>>>(ml.pptr, ml.S, ml.P, w.rowid[n]);
             TK_LAUNCH_CHECK("k_rowid");
         }
+    }
+    // position maps: mode 0's and mode n's padded streams sorted by the lexicographic key
+    const int64_t D = ctx->nnz;
+    if (D > 0 && N >= 2) {
+        uint64_t prod = 1;
+        for (int t = 0; t < N; ++t) prod *= (uint64_t)ctx->dims[t];   // < 2^63, checked at init
+        int bits = 1;
+        while (bits < 63 && ((prod >> bits) != 0)) ++bits;
+        const uint64_t pad = (bits >= 64) ? ~0ull : ((1ull << bits) - 1);   // > every real key
+        void *kin = nullptr, *kout = nullptr, *pin = nullptr, *pout = nullptr, *pos0 = nullptr, *tmp = nullptr;
+        size_t tmp_bytes = 0;
+        TK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                                  (int32_t*)nullptr, (int32_t*)nullptr, (int)maxP, 0, bits, s));
+        auto release = [&]() {
+            (void)hipStreamSynchronize(s);
+            void* ps[] = {kin, kout, pin, pout, pos0, tmp};
+            for (void* p : ps)
+                if (p) (void)hipFree(p);
+        };
+        if ((st = alloc(&kin, (size_t)maxP * 8)) || (st = alloc(&kout, (size_t)maxP * 8)) ||
+            (st = alloc(&pin, (size_t)maxP * 4)) || (st = alloc(&pout, (size_t)maxP * 4)) ||
+            (st = alloc(&pos0, (size_t)D * 4)) || (st = alloc(&tmp, tmp_bytes))) {
+            release();
+            return st;
+        }
+        for (int n = 0; n < N; ++n) {
+            const ModeLayout& ml = ctx->mode[n];
+            LexSpec ls{};
+            ls.N = N;
+            ls.m = n;
+            for (int t = 0; t < N; ++t) ls.dims[t] = ctx->dims[t];
+            for (int j = 0; j < N - 1; ++j) ls.others[j] = ml.others[j];
+            k_lex_keys<<<cdiv(ml.P, 256), 256, 0, s>>>(ls, w.rowid[n], ml.rows, ml.ptr, ml.pptr, ml.idx, ml.P, pad,
+                                                     (uint64_t*)kin, (int32_t*)pin);
+            if (hipGetLastError() != hipSuccess) {
+                release();
+                return set_error(TK_ERR_HIP, "k_lex_keys launch failed");
+            }
+            size_t tb = tmp_bytes;
+            if (hipcub::DeviceRadixSort::SortPairs(tmp, tb, (uint64_t*)kin, (uint64_t*)kout, (int32_t*)pin,
+                                                   (int32_t*)pout, (int)ml.P, 0, bits, s) != hipSuccess) {
+                release();
+                return set_error(TK_ERR_HIP, "position-map sort failed");
+            }
+            if (n == 0) {
+                if (hipMemcpyAsync(pos0, pout, (size_t)D * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+                    release();
+                    return set_error(TK_ERR_HIP, "position-map copy failed");
+                }
+                continue;
+            }
+            if ((st = alloc((void**)&w.map[n], (size_t)ml.P * 4))) {
+                release();
+                return st;
+            }
+            k_fill_i32<<<cdiv(ml.P, 256), 256, 0, s>>>(w.map[n], ml.P, -1);
+            k_map<<<cdiv(D, 256), 256, 0, s>>>((const int32_t*)pos0, (const int32_t*)pout, D, w.map[n]);
+            if (hipGetLastError() != hipSuccess) {
+                release();
+                return set_error(TK_ERR_HIP, "k_map launch failed");
+            }
+        }
+        release();
     }
     w.ready = true;
     return TK_OK;
@@ -423,9 +539,15 @@ int adjoint_typed(tk_ctx* ctx, const AT* G, const AT* const* U, AT* loss, AT* gG
         u.size = size;
         k_unfold<AT><<<cdiv(size, 256), 256, 0, s>>>(u, G, Gn);
         TK_LAUNCH_CHECK("k_unfold");
-        k_w<AT><<<cdiv(I * K, 256), 256, 0, s>>>(U[n], Gn, I, R, K, (AT*)w.W);
-        TK_LAUNCH_CHECK("k_w");
-        if (ml.P > 0) {
+        if (n > 0) {
+            // the residuals of mode 0's stream, in mode n's order
+            if (ml.P > 0) {
+                k_permute<AT><<<cdiv(ml.P, 256), 256, 0, s>>>(w.map[n], ml.P, (const AT*)w.e, (AT*)w.e2);
+                TK_LAUNCH_CHECK("k_permute");
+            }
+        } else if (ml.P > 0) {
+            k_w<AT><<<cdiv(I * K, 256), 256, 0, s>>>(U[n], Gn, I, R, K, (AT*)w.W);
+            TK_LAUNCH_CHECK("k_w");
             ResidArgs ra{};
             ra.rowid = w.rowid[n];
             ra.rows = ml.rows;
@@ -454,10 +576,10 @@ int adjoint_typed(tk_ctx* ctx, const AT* G, const AT* const* U, AT* loss, AT* gG
                 k_residual<AT><<<cdiv(ml.P, 256), 256, 0, s>>>(ra);
                 TK_LAUNCH_CHECK("k_residual");
             }
-            if (n == 0) nblk0 = (ml.P + 255) / 256;
+            nblk0 = (ml.P + 255) / 256;
         }
         // TTMc_n(E): the forward kernels with the residuals in place of the values
-        if ((st = ttmc_run(ctx, n, ctx->ws.y, s, nullptr, w.e))) return st;
+        if ((st = ttmc_run(ctx, n, ctx->ws.y, s, nullptr, n == 0 ? w.e : w.e2))) return st;
         const AT* Y = (const AT*)ctx->ws.y;
         if (R <= 16 && K % 4 == 0 && (size_t)R * K * sizeof(AT) <= 64 * 1024) {
             k_gu_rows<AT><<<cdiv(I, 256), 256, (size_t)R * K * sizeof(AT), s>>>(Y, Gn, I, R, (int)K, scale, gU[n]);
@@ -489,11 +611,13 @@ int adjoint_typed(tk_ctx* ctx, const AT* G, const AT* const* U, AT* loss, AT* gG
 
 void free_completion_ws(tk_ctx* ctx) {
     CompletionWs& w = ctx->cws;
-    void* ps[] = {w.e, w.W, w.Gn, w.part};
+    void* ps[] = {w.e, w.e2, w.W, w.Gn, w.part};
     for (void* p : ps)
         if (p) (void)hipFree(p);
-    for (int n = 0; n < kMaxOrder; ++n)
+    for (int n = 0; n < kMaxOrder; ++n) {
         if (w.rowid[n]) (void)hipFree(w.rowid[n]);
+        if (w.map[n]) (void)hipFree(w.map[n]);
+    }
     w = CompletionWs{};
 }
 

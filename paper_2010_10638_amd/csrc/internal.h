@@ -100,7 +100,9 @@ struct Workspace {
 struct CompletionWs {
     bool ready = false;
     int32_t* rowid[kMaxOrder] = {};  // per mode: compressed row of every padded position
-    void* e = nullptr;               // residuals on one mode's padded stream (parameter type)
+    void* e = nullptr;               // residuals on mode 0's padded stream (parameter type)
+    void* e2 = nullptr;              // the same residuals on mode n's padded stream, n >= 1
+    int32_t* map[kMaxOrder] = {};    // n >= 1: mode-0 padded position of every padded position of mode n (-1: pad)
     void* W = nullptr;               // U_n G_(n), max_n I_n x K_n
     void* Gn = nullptr;              // mode-n unfolding of the core
     double* part = nullptr;          // loss and core-gradient partials
