@@ -219,10 +219,12 @@ int reconstruct(tk_ctx* ctx, const double* G, const double* const* U, int64_t m,
  *   loss   device scalar
  *   gG     device [prod R_k], written
  *   gU     host array of N device pointers, I_k x R_k, written
- * Every pointer is caller-owned; the work is enqueued on `stream` without synchronisation.  The
- * first call allocates the completion workspace (the row of every padded position of each mode,
- * one mode's residuals, U_n G_(n)), held until tucker_free.  Sums run in a fixed order, so the
- * results are deterministic.  Errors: TK_ERR_ARG (null pointer, dtype mismatch),
+ * Every pointer is caller-owned; the work is enqueued on `stream` without synchronisation,
+ * except in the first call.  That call allocates the completion workspace, held until
+ * tucker_free: the row of every padded position of each mode, the residuals in two stream orders,
+ * U_0 G_(0), and for every mode n >= 1 a map from its padded positions to mode 0's.  It builds the
+ * maps with radix sorts, synchronising the stream once to release their temporaries.  Sums run in
+ * a fixed order, so the results are deterministic.  Errors: TK_ERR_ARG (null pointer, dtype mismatch),
  * TK_ERR_UNSUPPORTED, TK_ERR_OOM, TK_ERR_HIP.
  */
 int ttmc_adjoint(tk_ctx* ctx, int dtype, const void* G, const void* const* U, void* loss, void* gG,
