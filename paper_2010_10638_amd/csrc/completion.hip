@@ -276,6 +276,37 @@ __global__ __launch_bounds__(256) void k_gu_rows(const AT* __restrict__ Y, const
         if (r < R) gU[i * R + r] = (AT)(scale * acc[r]);
 }
 
+// Same product for FP32, R <= 16, K % 16 == 0: a wave per 16 rows of Y on v_mfma_f64_16x16x4f64
+// (FP32 inputs widened, FP64 sums), Y read once with 16-byte loads.  Lane l = 16 g + c loads
+// columns 16 t + 4 g .. 16 t + 4 g + 3 of row c of the tile and of row c of Gn; the u-th of the
+// four MFMAs of block t takes the u-th of them (lane l supplies A[c][g] and B[g][c]), so the
+// contraction runs over the columns 16 t + 4 g + u.  Lane l holds D[g + 4 v][c] in result v.
+__global__ __launch_bounds__(256) void k_gu_mfma(const float* __restrict__ Y, const float* __restrict__ Gn,
+                                                 int64_t I, int R, int K, double scale, float* __restrict__ gU) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (row0 >= I) return;   // wave-uniform
+    const int c = lane & 15, g = lane >> 4;
+    const bool rok = row0 + c < I, gok = c < R;
+    const float* y = Y + (rok ? row0 + c : 0) * (int64_t)K + 4 * g;
+    const float* b = Gn + (int64_t)(gok ? c : 0) * K + 4 * g;
+    atb_d4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < K; t += 16) {
+        float4 yv = make_float4(0.f, 0.f, 0.f, 0.f), bv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (rok) yv = *(const float4*)(y + t);
+        if (gok) bv = *(const float4*)(b + t);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)yv.x, (double)bv.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)yv.y, (double)bv.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)yv.z, (double)bv.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)yv.w, (double)bv.w, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t r = row0 + g + 4 * v;
+        if (r < I && c < R) gU[r * R + c] = (float)(scale * acc[v]);
+    }
+}
+
 // part[split][r][c] = sum_{i in slab} U[i][r] Y[i][c] on FP64 MFMA (same blocking as the core)
 template <typename AT>
 __global__ __launch_bounds__(256) void k_gg_partial(const AT* __restrict__ Y, const AT* __restrict__ U,
@@ -581,7 +612,11 @@ int adjoint_typed(tk_ctx* ctx, const AT* G, const AT* const* U, AT* loss, AT* gG
         // TTMc_n(E): the forward kernels with the residuals in place of the values
         if ((st = ttmc_run(ctx, n, ctx->ws.y, s, nullptr, n == 0 ? w.e : w.e2))) return st;
         const AT* Y = (const AT*)ctx->ws.y;
-        if (R <= 16 && K % 4 == 0 && (size_t)R * K * sizeof(AT) <= 64 * 1024) {
+        if (std::is_same<AT, float>::value && R <= 16 && K % 16 == 0) {
+            k_gu_mfma<<<cdiv(I, 64), 256, 0, s>>>((const float*)Y, (const float*)Gn, I, R, (int)K, scale,
+                                                  (float*)gU[n]);
+            TK_LAUNCH_CHECK("k_gu_mfma");
+        } else if (R <= 16 && K % 4 == 0 && (size_t)R * K * sizeof(AT) <= 64 * 1024) {
             k_gu_rows<AT><<<cdiv(I, 256), 256, (size_t)R * K * sizeof(AT), s>>>(Y, Gn, I, R, (int)K, scale, gU[n]);
             TK_LAUNCH_CHECK("k_gu_rows");
         } else {
