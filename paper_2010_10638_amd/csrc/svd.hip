@@ -18,6 +18,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -519,6 +520,46 @@ __global__ __launch_bounds__(128) void k_svd_left(const YT* __restrict__ Y, int6
         if (r < R) U[i * R + r] = (sq[r] > 0.0) ? acc[r] / sq[r] : 0.0;
 }
 
+// The same for FP32 Y, R <= 16, K % 16 == 0: a wave per 16 rows of Y on v_mfma_f64_16x16x4f64
+// (FP64 sums), Y read once with 16-byte loads.  Lane l = 16 g + c loads columns
+// 16 t + 4 g .. 16 t + 4 g + 3 of row c of the tile and of eigenvector c; the u-th of the four
+// MFMAs of block t takes the u-th of them (lane l supplies A[c][g] and B[g][c]), so the
+// contraction runs over the columns 16 t + 4 g + u.  Lane l holds D[g + 4 v][c] in result v.
+typedef double svd_d4_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_svd_left_mfma(const float* __restrict__ Y, int64_t I, int K,
+                                                       const double* __restrict__ V, const double* __restrict__ D,
+                                                       int desc, int R, double* __restrict__ U) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (row0 >= I) return;   // wave-uniform
+    const int c = lane & 15, g = lane >> 4;
+    const bool rok = row0 + c < I, vok = c < R;
+    const float* y = Y + (rok ? row0 + c : 0) * (int64_t)K + 4 * g;
+    const double* v = V + (vok ? eig_index(c, K, desc) : 0) * K + 4 * g;
+    svd_d4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < K; t += 16) {
+        float4 yv = make_float4(0.f, 0.f, 0.f, 0.f);
+        double2 v01 = make_double2(0.0, 0.0), v23 = make_double2(0.0, 0.0);
+        if (rok) yv = *(const float4*)(y + t);
+        if (vok) {
+            v01 = *(const double2*)(v + t);
+            v23 = *(const double2*)(v + t + 2);
+        }
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)yv.x, v01.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)yv.y, v01.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)yv.z, v23.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)yv.w, v23.y, acc, 0, 0, 0);
+    }
+    if (!vok) return;
+    const double lam = D[eig_index(c, K, desc)];
+    const double sq = (lam > 0.0) ? sqrt(lam) : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t r = row0 + g + 4 * q;
+        if (r < I) U[r * R + c] = (sq > 0.0) ? acc[q] / sq : 0.0;
+    }
+}
+
 // Fat case: U[i][r] = entry i of the r-th leading eigenvector of Y Y^T.
 __global__ void k_svd_fat(const double* __restrict__ V, int64_t I, int desc, int R, double* __restrict__ U) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -561,7 +602,10 @@ int left_typed(const tk_ctx* ctx, int mode, const YT* Y, const double* V, const 
                double* U, hipStream_t s) {
     const int64_t I = ctx->dims[mode];
     const int K = (int)ctx->mode[mode].K, R = ctx->ranks[mode];
-    if (R <= 8) k_svd_left<YT, 8><<<cdiv(I, 128), 128, 0, s>>>(Y, I, K, V, D, desc, R, U);
+    if (std::is_same<YT, float>::value && R <= 16 && K % 16 == 0 && ((uintptr_t)V % 16) == 0 &&
+        ((uintptr_t)Y % 16) == 0)
+        k_svd_left_mfma<<<cdiv(I, 64), 256, 0, s>>>((const float*)Y, I, K, V, D, desc, R, U);
+    else if (R <= 8) k_svd_left<YT, 8><<<cdiv(I, 128), 128, 0, s>>>(Y, I, K, V, D, desc, R, U);
     else if (R <= 16) k_svd_left<YT, 16><<<cdiv(I, 128), 128, 0, s>>>(Y, I, K, V, D, desc, R, U);
     else k_svd_left<YT, 32><<<cdiv(I, 128), 128, 0, s>>>(Y, I, K, V, D, desc, R, U);
     TK_LAUNCH_CHECK("k_svd_left");
