@@ -570,31 +570,37 @@ __global__ void k_svd_fat(const double* __restrict__ V, int64_t I, int desc, int
 }
 
 // Sign convention: in each column the entry of largest magnitude (the first one on ties) made
-// positive.  One workgroup per column.
-__global__ __launch_bounds__(256) void k_svd_sign(double* __restrict__ U, int64_t I, int R) {
-    __shared__ double s_v[256];
-    __shared__ int64_t s_i[256];
+// positive.  One workgroup of 1024 threads per column: a (value, row) reduction per wave by
+// shuffles, then over the waves in order.
+__global__ __launch_bounds__(1024) void k_svd_sign(double* __restrict__ U, int64_t I, int R) {
+    __shared__ double s_v[16];
+    __shared__ int64_t s_i[16];
     __shared__ int s_flip;
-    const int r = blockIdx.x;
+    const int r = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
     double best = -1.0;
     int64_t bi = 0;
-    for (int64_t i = threadIdx.x; i < I; i += blockDim.x) {
+    for (int64_t i = t; i < I; i += 1024) {
         const double v = fabs(U[i * R + r]);
         if (v > best) { best = v; bi = i; }
     }
-    s_v[threadIdx.x] = best;
-    s_i[threadIdx.x] = bi;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double ov = __shfl_xor(best, o);
+        const int64_t oi = __shfl_xor(bi, o);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (lane == 0) { s_v[w] = best; s_i[w] = bi; }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         double b = s_v[0];
         int64_t ii = s_i[0];
-        for (int t = 1; t < (int)blockDim.x; ++t)
-            if (s_v[t] > b || (s_v[t] == b && s_i[t] < ii)) { b = s_v[t]; ii = s_i[t]; }
+        for (int q = 1; q < 16; ++q)
+            if (s_v[q] > b || (s_v[q] == b && s_i[q] < ii)) { b = s_v[q]; ii = s_i[q]; }
         s_flip = (U[ii * R + r] < 0.0) ? 1 : 0;
     }
     __syncthreads();
     if (s_flip)
-        for (int64_t i = threadIdx.x; i < I; i += blockDim.x) U[i * R + r] = -U[i * R + r];
+        for (int64_t i = t; i < I; i += 1024) U[i * R + r] = -U[i * R + r];
 }
 
 template <typename YT>
@@ -640,7 +646,7 @@ static int svd_finish(tk_ctx* ctx, int mode, const void* Y, const double* V, con
     } else {
         if ((st = left_typed<float>(ctx, mode, (const float*)Y, V, D, desc, U, s))) return st;
     }
-    k_svd_sign<<<(unsigned)R, 256, 0, s>>>(U, I, R);
+    k_svd_sign<<<(unsigned)R, 1024, 0, s>>>(U, I, R);
     TK_LAUNCH_CHECK("k_svd_sign");
     return convert_factor(ctx, mode, U, s);
 }
