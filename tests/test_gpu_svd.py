@@ -127,3 +127,22 @@ def test_svd_unsupported_shape(tk):
     with pytest.raises(tk.TuckerError) as e:
         tk.svd_update(ctx, 0, Y)
     assert e.value.status == 5
+
+
+def test_hooi_run_svd(tk):
+    """hooi_run on a context with the SVD update: fits match the oracle's SVD-HOOI sweeps, never
+    decrease, and the run stops at the first sweep whose fit changed by at most tol."""
+    dims, ranks = [120, 100, 80], [6, 5, 4]
+    w = synth.small_uniform(32, dims, ranks, 15000)
+    tol = 5e-5   # the fit changes by 4.5e-5 at the 7th sweep on this tensor
+    ctx = make(tk, w, "f64", svd=True)
+    U = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in w.U_init]
+    G, fits = tk.hooi_run(ctx, U, max_sweeps=12, tol=tol)
+    assert len(fits) == 7, fits
+    check_solver(tk, ctx, "own")
+    _, _, fo = oracle.hooi_svd(w.coords, w.vals, dims, ranks, w.U_init, len(fits))
+    np.testing.assert_allclose(fits, fo, rtol=1e-10, atol=0)
+    assert all(b >= a - 1e-13 for a, b in zip(fits, fits[1:])), fits
+    for s in range(1, len(fits) - 1):
+        assert abs(fits[s] - fits[s - 1]) > tol
+    assert abs(fits[-1] - fits[-2]) <= tol
