@@ -1,11 +1,15 @@
 """Benchmark: HOOI sweeps of sparse Tucker on one MI355X.
 
 One step = one full sweep of the hot path: for every mode the sparse TTMc, the FP64 QRP that
-refreshes U_n, then the core and the fit, on the order-3 low-rank workload
-(10,000^3, 10M nonzeros, ranks 16, FP32 TTMc / FP64 QRP).  Inputs are resident in HBM before
-timing starts.  Prints one JSON line.
+refreshes U_n, then the core and the fit.  The default workload is the recommendation-shaped
+order-3 tensor (500,000 x 100,000 x 365, 50M nonzeros with Zipf(1.2) indices on the first two
+modes, log-normal values, ranks 10, FP32 TTMc / FP64 QRP, 5 sweeps from the seeded factors).
+Inputs are resident in HBM before timing starts.  Prints one JSON line; besides the metric it
+carries the roofline of the TTMc kernel, the same sweeps with the BF16-operand TTMc, the time to
+reach the FP64 oracle's final fit (stored by tests/golden/make_fullsize_fits.py), the low-rank
+10,000^3 workload's sweep, and the oracle timed on the host's cores.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu-baseline] [--workload ...]
 """
 from __future__ import annotations
 
@@ -21,10 +25,14 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
-# rocprofv3 FETCH_SIZE / WRITE_SIZE counters of the dominant kernel on this workload, with the
-# source hash of the kernel file they were taken on (traffic is reported only while it matches)
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_ttmc3_lds_f32_lowrank_10000cube_10M_r16.md")
+# rocprofv3 FETCH_SIZE / WRITE_SIZE counters of the dominant kernel on the default workload, with
+# the source hash of the kernel file they were taken on (traffic is reported only while it matches)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_ttmc3_lds_f32_zipf_500000x100000x365_50M_r10.md")
 TTMC_SOURCE = os.path.join(ROOT, "paper_2010_10638_amd", "csrc", "ttmc.hip")
+# the FP64 oracle's fit sequences on the full-size workloads (written by a script that calls only
+# the oracle and the input generator)
+ORACLE_FITS = os.path.join(ROOT, "tests", "golden", "fullsize_fits.json")
+FIT_TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2}
 
 
 def alg_bytes_ttmc(ctx, info, nnz, mode, val_bytes, fac_bytes, y_bytes):
@@ -41,20 +49,61 @@ def alg_bytes_ttmc(ctx, info, nnz, mode, val_bytes, fac_bytes, y_bytes):
     return b
 
 
-def cpu_baseline(w, budget_s=10.0):
+def host_info():
+    """CPU model and the host threads this process may use (OMP_NUM_THREADS caps them)."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0))
+    omp = int(os.environ.get("OMP_NUM_THREADS") or avail)
+    return model, avail, max(1, min(avail, omp))
+
+
+def cpu_baseline(w):
+    """The FP64 oracle on the host, on a bounded sample of the same workload: one TTMc per mode
+    on all usable cores (row-partitioned, same arithmetic as the single-threaded oracle), the QRP
+    of each mode's Y_(n) (on a row sample for modes above 100,000 rows, scaled by the row count:
+    Householder QRP with R_n steps costs rows x K_n x R_n), the core, and one TTMc single-threaded.
+    Value: nnz * K_n updates per second of the resulting all-core sweep."""
+    import numpy as np
     import oracle
     oracle.build()
+    model, avail, threads = host_info()
+    N = len(w.dims)
+    t_ttmc, t_qrp, qrp_note = [], [], []
+    Y = None
+    for n in range(N):
+        t0 = time.perf_counter()
+        Y = oracle.ttmc(w.coords, w.vals, w.dims, w.ranks, n, w.U_init, threads=threads)
+        t_ttmc.append(time.perf_counter() - t0)
+        rows = Y.shape[0]
+        m = rows if rows <= 100_000 else 50_000
+        t0 = time.perf_counter()
+        oracle.factor(np.ascontiguousarray(Y[:m]), int(w.ranks[n]))
+        t_qrp.append((time.perf_counter() - t0) * rows / m)
+        qrp_note.append("all rows" if m == rows else f"{m} of {rows} rows, scaled")
     t0 = time.perf_counter()
-    sweeps = 0
-    U = w.U_init
-    while sweeps == 0 or (time.perf_counter() - t0 < budget_s and sweeps < 3):
-        U, _, _, _ = oracle.hooi(w.coords, w.vals, w.dims, w.ranks, U, 1)
-        sweeps += 1
-    dt = time.perf_counter() - t0
-    upd = sum(w.nnz * _K(w.ranks, n) for n in range(len(w.dims))) * sweeps
-    return dict(value=upd / dt, unit="updates/s", cores=1, kind="oracle",
-                sample=f"{sweeps} full HOOI sweep(s) of the same tensor (all modes: TTMc + QRP + core), "
-                       f"single-threaded FP64 C oracle, {dt:.1f} s")
+    oracle.core(Y, w.U_init[N - 1], w.ranks)
+    t_core = time.perf_counter() - t0
+    # single-threaded TTMc of the last mode
+    t0 = time.perf_counter()
+    oracle.ttmc(w.coords, w.vals, w.dims, w.ranks, N - 1, w.U_init)
+    t_single = time.perf_counter() - t0
+    upd = [w.nnz * _K(w.ranks, n) for n in range(N)]
+    sweep_s = sum(t_ttmc) + sum(t_qrp) + t_core
+    return dict(value=sum(upd) / sweep_s, unit="updates/s", cores=threads, kind="oracle",
+                sample=f"one FP64 oracle sweep of the same tensor from the seeded factors: TTMc of every "
+                       f"mode on {threads} threads (row-partitioned), QRP per mode ({'; '.join(qrp_note)}), core; "
+                       f"plus one single-threaded TTMc of mode {N - 1}",
+                cpu_model=model, cpus_visible=avail, sweep_s=sweep_s,
+                ttmc_s_per_mode=t_ttmc, qrp_s_per_mode=t_qrp, core_s=t_core,
+                single_thread={"mode": N - 1, "ttmc_s": t_single, "ttmc_updates_per_s": upd[N - 1] / t_single})
 
 
 def _sha256(path):
@@ -121,6 +170,19 @@ def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel):
     ])
 
 
+def oracle_fits(name):
+    """The oracle's stored fit sequence for a workload name (its TTMc-type suffix dropped)."""
+    if not os.path.exists(ORACLE_FITS):
+        return None
+    base = name.rsplit("_", 1)[0] if name.endswith(("_f32", "_bf16", "_f64")) else name
+    with open(ORACLE_FITS) as f:
+        data = json.load(f)["workloads"]
+    for key in (name, base):
+        if key in data:
+            return data[key]["fits"]
+    return None
+
+
 def ttmc_kernel_name(w):
     if len(w.dims) == 3 and max(w.ranks) <= 16:
         return {"f64": "k_ttmc3_mfma<double,double>", "f32": "k_ttmc3_lds<float>", "bf16": "k_ttmc3_lds<bf16>"}[w.dtype]
@@ -130,22 +192,24 @@ def ttmc_kernel_name(w):
 
 
 def roofline(w, N, flops, bytes_, t_launch, default):
-    """Roofline object of the dominant kernel.  The bench workload's TTMc does 2*K_n flops per
-    12 bytes of stream (intensity ~39 flop/B, above the FP32 ridge of 19.7): MFMA-bound; the
-    skewed and order-4 (fiber-factored) TTMcs are HBM-bound; the FP64 200^3 case is latency-bound
-    and reported against FP64 MFMA."""
+    """Roofline object of the dominant kernel (the TTMc, one launch per mode; figures averaged over
+    the modes).  Intensity = 2 K_n flops per nonzero over the stream bytes: the recommendation-shaped
+    tensor (K_n = 100, about 14 flop/B) sits below the FP32 ridge of 19.7 flop/B and is reported
+    against HBM; the low-rank tensor (K_n = 256, about 39 flop/B) against FP32 MFMA; the FP64 200^3
+    case against FP64 MFMA (it is latency-bound)."""
     gbs = bytes_ / t_launch / 1e9
     tflops = flops / t_launch / 1e12
     common = {"kernel": ttmc_kernel_name(w), "flops_per_launch": flops, "alg_bytes_per_launch": bytes_,
-              "avg_launch_ms": t_launch * 1e3, "hbm_gbs_alg": gbs, "hbm_frac_alg": gbs / PEAK_HBM_GBS}
+              "avg_launch_ms": t_launch * 1e3, "hbm_gbs_alg": gbs, "hbm_frac_alg": gbs / PEAK_HBM_GBS,
+              "tflops": tflops}
     if w.dtype == "f64":
         return {"bound": "mfma", "achieved": tflops, "peak": 78.6, "unit": "TFLOP/s", "frac": tflops / 78.6,
                 "traffic": None, **common}
     if flops / bytes_ > PEAK_FP32_MFMA_TFLOPS / (PEAK_HBM_GBS / 1e3) and N == 3:
         return {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": tflops / PEAK_FP32_MFMA_TFLOPS, "traffic": measured_traffic() if default else None, **common}
+                "frac": tflops / PEAK_FP32_MFMA_TFLOPS, "traffic": None, **common}
     return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-            "traffic": None, **common}
+            "traffic": measured_traffic() if default else None, **common}
 
 
 def compare_precisions(args, w, tk, torch):
@@ -240,18 +304,102 @@ def _K(ranks, n):
     return k
 
 
+def run_sweeps(args, w, tk, torch, profile=True):
+    """Layout build, warm-up, then args.steps timed HOOI sweeps (and the same number again with
+    region events for the breakdown).  Returns the measurements and the context."""
+    coords = torch.from_numpy(w.coords).cuda()
+    vals = torch.from_numpy(w.vals).cuda()
+    ctx = tk.tucker_init(coords, vals, w.dims, w.ranks, dtype=w.dtype, svd=args.factor == "svd")
+    del coords, vals
+    info = tk.tucker_get_info(ctx)
+    U = [torch.from_numpy(u).cuda() for u in w.U_init]
+    G = torch.empty(w.ranks, dtype=torch.float64, device="cuda")
+    fit = torch.empty(1, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        tk.hooi_sweep(ctx, U, G, fit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tk.hooi_sweep(ctx, U, G, fit)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = {"ctx": ctx, "info": info, "sweep_s": (t1 - t0) / args.steps, "fit": float(fit.item())}
+    if profile:
+        # the same number of sweeps again with HIP events on the sweep's stream around every
+        # region and around each main TTMc kernel (breakdown and roofline; not the timed value)
+        tk.tucker_profile(ctx, args.steps)
+        for _ in range(args.steps):
+            tk.hooi_sweep(ctx, U, G, fit)
+        out["prof"] = tk.tucker_profile_read(ctx)
+        tk.tucker_profile(ctx, 0)
+    return out
+
+
+def fits_from_start(w, ctx, tk, torch):
+    """w.sweeps synchronised sweeps from the seeded factors: per-sweep wall time and fit, and the
+    time to reach the FP64 oracle's final fit (stored) within the TTMc type's tolerance."""
+    U = [torch.from_numpy(u).cuda() for u in w.U_init]
+    G = torch.empty(w.ranks, dtype=torch.float64, device="cuda")
+    fit = torch.empty(1, dtype=torch.float64, device="cuda")
+    fits, times = [], []
+    for _ in range(w.sweeps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tk.hooi_sweep(ctx, U, G, fit)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        fits.append(float(fit.item()))
+    res = {"sweeps": w.sweeps, "fits": fits, "sweep_ms": [t * 1e3 for t in times]}
+    ref = oracle_fits(w.name)
+    if ref is not None and len(ref) == len(fits):
+        tol = FIT_TOL[w.dtype]
+        target = ref[-1]
+        res["oracle_fits"] = ref
+        res["fit_rel_err_vs_oracle"] = [abs(a - b) / abs(b) for a, b in zip(fits, ref)]
+        res["tolerance"] = tol
+        hit = next((k for k, f in enumerate(fits) if abs(f - target) <= tol * abs(target)), None)
+        res["sweeps_to_oracle_final_fit"] = None if hit is None else hit + 1
+        res["ms_to_oracle_final_fit"] = None if hit is None else sum(times[:hit + 1]) * 1e3
+    return res
+
+
+def ttmc_roofline(w, r):
+    """Algorithmic bytes and flops per TTMc launch (averaged over the modes) and the main kernel's
+    average duration from the region events."""
+    ctx, info, prof = r["ctx"], r["info"], r["prof"]
+    N = len(w.dims)
+    nnz = info["nnz"]
+    val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[w.dtype]
+    y_bytes = 8 if w.dtype == "f64" else 4
+    kern_s = sum(prof["ttmc_kernel_ms"]) / 1e3 / prof["sweeps"]
+    flops = sum(2 * nnz * _K(w.ranks, n) for n in range(N)) / N
+    bytes_ = sum(alg_bytes_ttmc(ctx, info, nnz, n, val_bytes, val_bytes, y_bytes) for n in range(N)) / N
+    return flops, bytes_, kern_s / N
+
+
+def breakdown(r):
+    prof = r["prof"]
+    ns = prof["sweeps"]
+    return {"ttmc": sum(prof["ttmc_ms"]) / ns, "qrp": sum(prof["qrp_ms"]) / ns, "core_fit": prof["core_ms"] / ns,
+            "ttmc_per_mode": [x / ns for x in prof["ttmc_ms"]],
+            "ttmc_kernel_per_mode": [x / ns for x in prof["ttmc_kernel_ms"]],
+            "qrp_per_mode": [x / ns for x in prof["qrp_ms"]]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the workload's own sweeps (no BF16 rerun, no low-rank line, no fits from the start)")
     ap.add_argument("--small", action="store_true", help="small tensor (for profiling dry runs)")
-    ap.add_argument("--workload", default="lowrank",
-                    choices=["lowrank", "hooi200", "skewed-f32", "skewed-bf16", "order4-f32", "order4-bf16",
+    ap.add_argument("--workload", default="skewed-f32",
+                    choices=["skewed-f32", "skewed-bf16", "lowrank", "hooi200", "order4-f32", "order4-bf16",
                              "completion"],
-                    help="lowrank (default): 10,000^3, 10M nnz, R 16, FP32 TTMc; hooi200: 200^3, 20,000 nnz, "
-                    "R 8, FP64; skewed-*: 500,000 x 100,000 x 365, 50M Zipf nnz, R 10; order4-*: "
+                    help="skewed-* (default FP32): 500,000 x 100,000 x 365, 50M Zipf nnz, R 10; lowrank: "
+                    "10,000^3, 10M nnz, R 16, FP32 TTMc; hooi200: 200^3, 20,000 nnz, R 8, FP64; order4-*: "
                     "50,000 x 50,000 x 5,000 x 100, 20M nnz, R 8; completion: 100,000 x 100,000 x 1,000, "
                     "30M entries, R 16, one Adam step of the completion loss per step")
     ap.add_argument("--factor", default="qrp", choices=["qrp", "svd"],
@@ -279,7 +427,6 @@ def main():
               "shard by output rows, the QRP by an all-reduce of the Gram matrix).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -315,62 +462,23 @@ def main():
         return run_completion(args, w, tk, torch)
     if args.compare_precisions:
         return compare_precisions(args, w, tk, torch)
-    coords = torch.from_numpy(w.coords).cuda()
-    vals = torch.from_numpy(w.vals).cuda()
-    ctx = tk.tucker_init(coords, vals, w.dims, w.ranks, dtype=w.dtype, svd=args.factor == "svd")
-    del coords, vals
-    info = tk.tucker_get_info(ctx)
-    U = [torch.from_numpy(u).cuda() for u in w.U_init]
-    G = torch.empty(w.ranks, dtype=torch.float64, device="cuda")
-    fit = torch.empty(1, dtype=torch.float64, device="cuda")
 
-    for _ in range(args.warmup):
-        tk.hooi_sweep(ctx, U, G, fit)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        tk.hooi_sweep(ctx, U, G, fit)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    print(f"# timed {args.steps} sweeps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
-    # the same number of sweeps again with HIP events on the sweep's stream around every region
-    # and around each main TTMc kernel (breakdown and roofline; not part of the timed value)
-    tk.tucker_profile(ctx, args.steps)
-    for _ in range(args.steps):
-        tk.hooi_sweep(ctx, U, G, fit)
-    prof = tk.tucker_profile_read(ctx)
-    tk.tucker_profile(ctx, 0)
-
+    r = run_sweeps(args, w, tk, torch)
+    print(f"# timed {args.steps} sweeps: {r['sweep_s'] * 1e3:.3f} ms per sweep", file=sys.stderr, flush=True)
     N = len(w.dims)
-    nnz = info["nnz"]
+    nnz = r["info"]["nnz"]
     upd_per_sweep = sum(nnz * _K(w.ranks, n) for n in range(N))
-    sweep_s = (t1 - t0) / args.steps
-    value = upd_per_sweep / sweep_s
-
-    # dominant kernel: the TTMc (one launch per mode per sweep)
-    default = args.workload == "lowrank" and not args.small and args.factor == "qrp"
-    val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[w.dtype]
-    fac_bytes = val_bytes
-    y_bytes = 8 if w.dtype == "f64" else 4
-    ttmc_s = sum(prof["ttmc_ms"]) / 1e3 / prof["sweeps"]          # per sweep, all modes
-    kern_s = sum(prof["ttmc_kernel_ms"]) / 1e3 / prof["sweeps"]   # main kernel only
-    launches = N
-    flops = sum(2 * nnz * _K(w.ranks, n) for n in range(N)) / launches
-    bytes_ = sum(alg_bytes_ttmc(ctx, info, nnz, n, val_bytes, fac_bytes, y_bytes) for n in range(N)) / launches
-    t_launch = kern_s / launches
-    tflops = flops / t_launch / 1e12
-    gbs = bytes_ / t_launch / 1e9
-    qrp_s = sum(prof["qrp_ms"]) / 1e3 / prof["sweeps"]
-    core_s = prof["core_ms"] / 1e3 / prof["sweeps"]
-
+    flops, bytes_, t_launch = ttmc_roofline(w, r)
+    default = args.workload == "skewed-f32" and not args.small and args.factor == "qrp"
+    bd = breakdown(r)
     out = {
         "metric": "TTMc nnz*prod(R) updates/s over whole HOOI sweeps (TTMc + FP64 %s + core)" % args.factor.upper(),
-        "value": value,
+        "value": upd_per_sweep / r["sweep_s"],
         "unit": "updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sweep_s * 1e3,
+        "ms_per_step": r["sweep_s"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -379,16 +487,38 @@ def main():
         "config": {"workload": w.name, "dims": w.dims, "ranks": w.ranks, "nnz": nnz,
                    "ttmc": w.dtype, "qrp": "f64", "factor_update": args.factor, "parallelism": "single-gpu"},
         "roofline": roofline(w, N, flops, bytes_, t_launch, default),
-        "breakdown_ms_per_sweep": {"ttmc": ttmc_s * 1e3, "qrp": qrp_s * 1e3, "core_fit": core_s * 1e3,
-                                   "ttmc_per_mode": [x / prof["sweeps"] for x in prof["ttmc_ms"]],
-                                   "ttmc_kernel_per_mode": [x / prof["sweeps"] for x in prof["ttmc_kernel_ms"]],
-                                   "qrp_per_mode": [x / prof["sweeps"] for x in prof["qrp_ms"]]},
-        "ttmc_updates_per_s": upd_per_sweep / ttmc_s,
-        "fit": float(fit.item()),
+        "breakdown_ms_per_sweep": bd,
+        "ttmc_updates_per_s": upd_per_sweep / (bd["ttmc"] / 1e3),
+        "fit": r["fit"],
     }
+    if not args.no_extras and not args.small:
+        out["from_start"] = fits_from_start(w, r["ctx"], tk, torch)
+        if args.workload.startswith("skewed") and args.factor == "qrp":
+            # the same tensor and sweeps with the other TTMc type (BF16 operands / FP32 accumulation)
+            other = "bf16" if w.dtype == "f32" else "f32"
+            w2 = synth.Workload(w.name.rsplit("_", 1)[0] + "_" + other, w.dims, w.ranks, w.coords, w.vals,
+                                w.U_init, sweeps=w.sweeps, dtype=other)
+            del r["ctx"]
+            r2 = run_sweeps(args, w2, tk, torch)
+            f2, b2, t2 = ttmc_roofline(w2, r2)
+            out[other] = {"ms_per_step": r2["sweep_s"] * 1e3, "value": upd_per_sweep / r2["sweep_s"],
+                          "breakdown_ms_per_sweep": breakdown(r2), "hbm_frac_alg": b2 / t2 / 1e9 / PEAK_HBM_GBS,
+                          "from_start": fits_from_start(w2, r2["ctx"], tk, torch)}
+            del r2
+        if default:
+            # the low-rank 10,000^3 workload (10M nonzeros, ranks 16, FP32 TTMc) as a second line
+            w3 = synth.lowrank_f32()
+            r3 = run_sweeps(args, w3, tk, torch)
+            f3, b3, t3 = ttmc_roofline(w3, r3)
+            upd3 = sum(r3["info"]["nnz"] * _K(w3.ranks, n) for n in range(3))
+            out["lowrank_f32"] = {"workload": w3.name, "ms_per_step": r3["sweep_s"] * 1e3,
+                                  "value": upd3 / r3["sweep_s"], "ttmc_kernel_us": t3 * 1e6,
+                                  "mfma_frac": f3 / t3 / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                                  "hbm_frac_alg": b3 / t3 / 1e9 / PEAK_HBM_GBS,
+                                  "from_start": fits_from_start(w3, r3["ctx"], tk, torch)}
+            del r3
     if not args.no_cpu_baseline and default:
         out["cpu_baseline"] = cpu_baseline(w)
-        out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
     print(json.dumps(out), flush=True)
 
 

@@ -18,6 +18,11 @@
  *     caller; the library owns only what hangs off a tk_ctx and frees it in tucker_free.
  *   - stream is a hipStream_t passed as void* (NULL = the default stream).  Work is enqueued
  *     asynchronously on it; only the calls documented as synchronising wait for the device.
+ *   - Every call on one context uses that context's scratch (factor copies, Y_(n), carry rows,
+ *     QRP, SVD and completion workspaces).  Calls on the same context must therefore be ordered:
+ *     issue them on one stream, or make each call's stream wait for the previous call's stream
+ *     (an event) before the call.  Concurrent calls on one context race; different contexts are
+ *     independent.
  *   - Indices are 0-based.  Modes are 0-based in the API (mode 0 is the paper's mode 1).
  *   - Matrices are row-major: U_k is I_k x R_k, Y_(n) is I_n x K_n with K_n = prod_{t != n} R_t.
  *   - The core G is stored C-order (last index fastest), R_1 x ... x R_N.
@@ -153,6 +158,18 @@ int svd_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, void* stream
  *                limits, or no convergence within its step limit)
  */
 int tucker_svd_info(const tk_ctx* ctx, int* outer_steps);
+
+/*
+ * tucker_qrp_gaps - pivot gaps of the last QRP of a mode (qrp_update or a sweep): gaps[j] =
+ * (d_j - d'_j) / d_j, where d_j is the squared norm of the trailing column chosen at step j of the
+ * pivoted factorization (Sec. III-D compares these norms) and d'_j the largest squared norm among
+ * the other candidates; 0 means a tie (decided by column position), small values mean that
+ * rounding of Y_(n) can change the pivot.  NaN where the route used does not record them (the
+ * Householder and fat-matrix routes, R_n > 32) or before the mode's first QRP.
+ *   gaps  host double[R_mode]
+ * Synchronises the stream of the context's last call.  Errors: TK_ERR_ARG, TK_ERR_HIP.
+ */
+int tucker_qrp_gaps(tk_ctx* ctx, int mode, double* gaps);
 
 /*
  * core_fit - G_(N) = U_N^T Y_(N) (Alg. 2, the step after the mode loop) and the fit.

@@ -34,7 +34,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         os.makedirs(_LIB_DIR, exist_ok=True)
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -47,12 +47,14 @@ def _load():
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
         lib.orc_ttmc.argtypes = [ctypes.c_int, P, P, I64, P, P, ctypes.c_int, P, P]
-        lib.orc_qrp.argtypes = [I64, I64, P, ctypes.c_int, P, P]
-        lib.orc_factor.argtypes = [I64, I64, P, ctypes.c_int, ctypes.c_int, P, P]
+        lib.orc_ttmc_threads.argtypes = [ctypes.c_int, P, P, I64, P, P, ctypes.c_int, P, P, ctypes.c_int]
+        lib.orc_qrp.argtypes = [I64, I64, P, ctypes.c_int, P, P, P]
+        lib.orc_factor.argtypes = [I64, I64, P, ctypes.c_int, ctypes.c_int, P, P, P]
         lib.orc_core.argtypes = [I64, I64, ctypes.c_int, P, P, P]
         lib.orc_fit.argtypes = [ctypes.c_double, P, I64]
         lib.orc_fit.restype = ctypes.c_double
-        lib.orc_hooi.argtypes = [ctypes.c_int, P, P, I64, P, P, P, ctypes.c_int, ctypes.c_int, P, P, P]
+        lib.orc_hooi.argtypes = [ctypes.c_int, P, P, I64, P, P, P, ctypes.c_int, ctypes.c_int, P, P, P,
+                                 ctypes.c_int]
         lib.orc_reconstruct.argtypes = [ctypes.c_int, P, P, P, I64, P, P]
         lib.orc_completion.argtypes = [ctypes.c_int, P, P, P, P, I64, P, P, P, P, P]
         _lib = lib
@@ -86,35 +88,45 @@ def kron_cols(ranks, mode) -> int:
     return int(np.prod([r for t, r in enumerate(ranks) if t != mode], dtype=np.int64))
 
 
-def ttmc(coords, vals, dims, ranks, mode: int, U) -> np.ndarray:
+def ttmc(coords, vals, dims, ranks, mode: int, U, threads: int = 1) -> np.ndarray:
     """Y_(mode) = X_(mode) (kron_{t != mode} U_t), Kronecker columns with the last mode fastest
-    (Alg. 2, per-nonzero update of Sec. III-C)."""
+    (Alg. 2, per-nonzero update of Sec. III-C).  threads > 1: the rows are split over that many
+    host threads, each row still summed in input order (bit-identical; for timing only)."""
     coords, vals, dims, ranks = _prep(coords, vals, dims, ranks)
     U = [np.ascontiguousarray(u, dtype=np.float64) for u in U]
     Y = np.empty((int(dims[mode]), kron_cols(ranks, mode)), dtype=np.float64)
-    _check(_load().orc_ttmc(dims.size, _p(dims), _p(ranks), vals.size, _p(coords), _p(vals), mode,
-                            _ptr_array(U), _p(Y)), "ttmc")
+    if threads > 1:
+        st = _load().orc_ttmc_threads(dims.size, _p(dims), _p(ranks), vals.size, _p(coords), _p(vals), mode,
+                                      _ptr_array(U), _p(Y), int(threads))
+    else:
+        st = _load().orc_ttmc(dims.size, _p(dims), _p(ranks), vals.size, _p(coords), _p(vals), mode,
+                              _ptr_array(U), _p(Y))
+    _check(st, "ttmc")
     return Y
 
 
-def qrp(A, R: int):
-    """First R columns of Q and the pivots of Householder QRP (Sec. III-D), R steps."""
+def qrp(A, R: int, gaps: bool = False):
+    """First R columns of Q and the pivots of Householder QRP (Sec. III-D), R steps; with gaps,
+    also the relative gap between the largest and second largest trailing norm at each step."""
     A = np.ascontiguousarray(A, dtype=np.float64)
     m, n = A.shape
     Q = np.empty((m, R), dtype=np.float64)
     piv = np.empty(R, dtype=np.int32)
-    _check(_load().orc_qrp(m, n, _p(A), R, _p(Q), _p(piv)), "qrp")
-    return Q, piv
+    g = np.empty(R, dtype=np.float64)
+    _check(_load().orc_qrp(m, n, _p(A), R, _p(Q), _p(piv), _p(g) if gaps else None), "qrp")
+    return (Q, piv, g) if gaps else (Q, piv)
 
 
-def factor(Y, R: int, fat_rule: bool = True):
-    """U_n <- QRP(Y_(n), R_n), with Y Y^T in place of a fat Y when fat_rule (Sec. III-D)."""
+def factor(Y, R: int, fat_rule: bool = True, gaps: bool = False):
+    """U_n <- QRP(Y_(n), R_n), with Y Y^T in place of a fat Y when fat_rule (Sec. III-D); with
+    gaps, also the per-step relative pivot gaps."""
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     I, K = Y.shape
     U = np.empty((I, R), dtype=np.float64)
     piv = np.empty(R, dtype=np.int32)
-    _check(_load().orc_factor(I, K, _p(Y), R, int(fat_rule), _p(U), _p(piv)), "factor")
-    return U, piv
+    g = np.empty(R, dtype=np.float64)
+    _check(_load().orc_factor(I, K, _p(Y), R, int(fat_rule), _p(U), _p(piv), _p(g) if gaps else None), "factor")
+    return (U, piv, g) if gaps else (U, piv)
 
 
 def core(Y_last, U_last, ranks) -> np.ndarray:
@@ -133,8 +145,9 @@ def fit(normX2: float, G) -> float:
     return float(_load().orc_fit(float(normX2), _p(G), G.size))
 
 
-def hooi(coords, vals, dims, ranks, U_init, sweeps: int, fat_rule: bool = True):
-    """Alg. 2 sweeps.  Returns (U list, G, fits[sweeps], pivots[sweeps, N, maxR])."""
+def hooi(coords, vals, dims, ranks, U_init, sweeps: int, fat_rule: bool = True, threads: int = 1):
+    """Alg. 2 sweeps.  Returns (U list, G, fits[sweeps], pivots[sweeps, N, maxR]).  threads > 1
+    runs the TTMc row-partitioned on that many host threads (same results)."""
     coords, vals, dims, ranks = _prep(coords, vals, dims, ranks)
     U = [np.array(u, dtype=np.float64, order="C", copy=True) for u in U_init]
     N = dims.size
@@ -143,7 +156,7 @@ def hooi(coords, vals, dims, ranks, U_init, sweeps: int, fat_rule: bool = True):
     maxR = int(ranks.max())
     pivs = np.full((sweeps, N, maxR), -1, dtype=np.int32)
     _check(_load().orc_hooi(N, _p(dims), _p(ranks), vals.size, _p(coords), _p(vals), _ptr_array(U),
-                            sweeps, int(fat_rule), _p(G), _p(fits), _p(pivs)), "hooi")
+                            sweeps, int(fat_rule), _p(G), _p(fits), _p(pivs), int(threads)), "hooi")
     return U, G.reshape(tuple(int(r) for r in ranks)), fits, pivs
 
 

@@ -14,6 +14,7 @@
  * modes are taken in ascending order and the LAST one varies fastest.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -69,16 +70,84 @@ int orc_ttmc(int N, const int64_t* dims, const int32_t* ranks, int64_t nnz,
 }
 
 /*
+ * The same TTMc on several host threads (used to time the CPU baseline on all cores; the
+ * arithmetic is orc_ttmc's).  The rows of Y_(n) are cut into nthreads ranges holding about equal
+ * numbers of nonzeros; each thread walks every nonzero in input order and applies only those whose
+ * row lies in its range.  Each row therefore receives the additions of orc_ttmc in the same order,
+ * so the result is bit-identical to orc_ttmc for any thread count.
+ */
+int orc_ttmc_threads(int N, const int64_t* dims, const int32_t* ranks, int64_t nnz,
+                     const int32_t* coords, const double* vals, int mode,
+                     const double* const* U, double* Y, int nthreads)
+{
+    if (N < 1 || mode < 0 || mode >= N || nthreads < 1) return ORC_ERR_ARG;
+    const int64_t K = kron_len(N, ranks, mode);
+    const int64_t I = dims[mode];
+    const int32_t* rowidx = coords + (int64_t)mode * nnz;
+    /* row ranges of about nnz / nthreads nonzeros each: bounds[k] .. bounds[k + 1] */
+    int64_t* count = (int64_t*)calloc((size_t)I + 1, sizeof(int64_t));
+    int64_t* bounds = (int64_t*)malloc((size_t)(nthreads + 1) * sizeof(int64_t));
+    if (!count || !bounds) { free(count); free(bounds); return ORC_ERR_OOM; }
+    for (int64_t p = 0; p < nnz; ++p) count[rowidx[p]] += 1;
+    bounds[0] = 0;
+    int64_t acc = 0, row = 0;
+    for (int k = 1; k < nthreads; ++k) {
+        const int64_t target = nnz * k / nthreads;
+        while (row < I && acc + count[row] <= target) acc += count[row++];
+        bounds[k] = row;
+    }
+    bounds[nthreads] = I;
+    int status = ORC_OK;
+#pragma omp parallel num_threads(nthreads)
+    {
+        const int k = omp_get_thread_num();
+        const int64_t lo = bounds[k], hi = bounds[k + 1];
+        double* kr = (double*)malloc((size_t)K * sizeof(double));
+        double* tmp = (double*)malloc((size_t)K * sizeof(double));
+        if (!kr || !tmp) {
+#pragma omp atomic write
+            status = ORC_ERR_OOM;
+        } else {
+            memset(Y + lo * K, 0, (size_t)((hi - lo) * K) * sizeof(double));
+            for (int64_t p = 0; p < nnz; ++p) {
+                const int64_t i = rowidx[p];
+                if (i < lo || i >= hi) continue;
+                int64_t len = 1;
+                kr[0] = vals[p];
+                for (int t = 0; t < N; ++t) {
+                    if (t == mode) continue;
+                    const int64_t R = ranks[t];
+                    const double* rw = U[t] + (int64_t)coords[(int64_t)t * nnz + p] * R;
+                    for (int64_t a = 0; a < len; ++a)
+                        for (int64_t b = 0; b < R; ++b)
+                            tmp[a * R + b] = kr[a] * rw[b];
+                    double* sw = kr; kr = tmp; tmp = sw;
+                    len *= R;
+                }
+                double* y = Y + i * K;
+                for (int64_t c = 0; c < K; ++c) y[c] += kr[c];
+            }
+        }
+        free(kr);
+        free(tmp);
+    }
+    free(count);
+    free(bounds);
+    return status;
+}
+
+/*
  * Householder QR with column pivoting (Sec. III-D), stopped after R steps.
  * A is m x n.  At step j the squared norms of the trailing sub-columns A[j:, c], c >= j, are
  * recomputed exactly; the first column of largest norm is swapped to position j (Businger-Golub
  * pivoting, giving |r_11| >= |r_22| >= ...).  The reflector is the textbook one:
  *     x = A[j:, j],  v = x + sgn(x_0) ||x|| e_1  (sgn(0) = +1),  H_j = I - 2 v v^T / (v^T v),
  * with H_j = I when x = 0.  Only the first R reflectors are formed, so this equals the first R
- * steps of the full factorization.  Output: Q[:, :R] = H_0 H_1 ... H_{R-1} [I_R; 0] (m x R) and
- * piv[j] = original index of the column placed at position j.
+ * steps of the full factorization.  Output: Q[:, :R] = H_0 H_1 ... H_{R-1} [I_R; 0] (m x R),
+ * piv[j] = original index of the column placed at position j, and (if gaps is not NULL) gaps[j] =
+ * the relative gap between the largest and the second largest trailing squared norm at step j.
  */
-int orc_qrp(int64_t m, int64_t n, const double* A_in, int R, double* Q, int32_t* piv)
+int orc_qrp(int64_t m, int64_t n, const double* A_in, int R, double* Q, int32_t* piv, double* gaps)
 {
     if (R < 1 || R > m || R > n) return ORC_ERR_ARG;
     double* A = (double*)malloc((size_t)(m * n) * sizeof(double));
@@ -96,12 +165,15 @@ int orc_qrp(int64_t m, int64_t n, const double* A_in, int R, double* Q, int32_t*
     for (int j = 0; j < R; ++j) {
         /* pivot: first column of largest trailing norm */
         int64_t p = j;
-        double best = -1.0;
+        double best = -1.0, second = -1.0;
         for (int64_t c = j; c < n; ++c) {
             double s = 0.0;
             for (int64_t i = j; i < m; ++i) s += A[i * n + c] * A[i * n + c];
-            if (s > best) { best = s; p = c; }
+            if (s > best) { second = best; best = s; p = c; }
+            else if (s > second) second = s;
         }
+        /* relative gap to the runner-up (1 when there is none, 0 for a tie) */
+        if (gaps) gaps[j] = (second < 0.0) ? 1.0 : (best > 0.0 ? (best - second) / best : 0.0);
         if (p != j) {
             for (int64_t i = 0; i < m; ++i) {
                 double t = A[i * n + j]; A[i * n + j] = A[i * n + p]; A[i * n + p] = t;
@@ -152,7 +224,7 @@ int orc_qrp(int64_t m, int64_t n, const double* A_in, int R, double* Q, int32_t*
  * Factor update U_n <- QRP(Y_(n), R_n) (Alg. 2).  With the fat-matrix rule of Sec. III-D, a Y
  * with more columns than rows is replaced by the square Y Y^T before the QRP.
  */
-int orc_factor(int64_t I, int64_t K, const double* Y, int R, int fat_rule, double* U, int32_t* piv)
+int orc_factor(int64_t I, int64_t K, const double* Y, int R, int fat_rule, double* U, int32_t* piv, double* gaps)
 {
     if (fat_rule && K > I) {
         double* A = (double*)malloc((size_t)(I * I) * sizeof(double));
@@ -163,11 +235,11 @@ int orc_factor(int64_t I, int64_t K, const double* Y, int R, int fat_rule, doubl
                 for (int64_t c = 0; c < K; ++c) s += Y[a * K + c] * Y[b * K + c];
                 A[a * I + b] = s;
             }
-        int st = orc_qrp(I, I, A, R, U, piv);
+        int st = orc_qrp(I, I, A, R, U, piv, gaps);
         free(A);
         return st;
     }
-    return orc_qrp(I, K, Y, R, U, piv);
+    return orc_qrp(I, K, Y, R, U, piv, gaps);
 }
 
 /*
@@ -200,11 +272,12 @@ double orc_fit(double normX2, const double* G, int64_t size)
  * Sparse Tucker sweeps (Alg. 2): for s in 1..sweeps, for n = 1..N: Y_(n) by TTMc with the current
  * factors (Gauss-Seidel: modes before n already updated this sweep), U_n <- QRP(Y_(n), R_n); after
  * the mode loop G from the last Y and fit.  U (N pointers) is updated in place.  fits[s] receives
- * the fit after sweep s; pivs (optional, sweeps x N x maxR) the pivot lists.
+ * the fit after sweep s; pivs (optional, sweeps x N x maxR) the pivot lists.  nthreads > 1 runs
+ * the TTMc on that many host threads (orc_ttmc_threads: the same result).
  */
 int orc_hooi(int N, const int64_t* dims, const int32_t* ranks, int64_t nnz,
              const int32_t* coords, const double* vals, double* const* U, int sweeps,
-             int fat_rule, double* G, double* fits, int32_t* pivs)
+             int fat_rule, double* G, double* fits, int32_t* pivs, int nthreads)
 {
     int maxR = 0;
     int64_t maxY = 0;
@@ -220,10 +293,12 @@ int orc_hooi(int N, const int64_t* dims, const int32_t* ranks, int64_t nnz,
     int64_t gsize = kron_len(N, ranks, -1);
     for (int s = 0; s < sweeps; ++s) {
         for (int n = 0; n < N; ++n) {
-            int st = orc_ttmc(N, dims, ranks, nnz, coords, vals, n, (const double* const*)U, Y);
+            int st = nthreads > 1
+                ? orc_ttmc_threads(N, dims, ranks, nnz, coords, vals, n, (const double* const*)U, Y, nthreads)
+                : orc_ttmc(N, dims, ranks, nnz, coords, vals, n, (const double* const*)U, Y);
             if (st) { free(Y); return st; }
             int32_t* pv = pivs ? pivs + ((int64_t)s * N + n) * maxR : NULL;
-            st = orc_factor(dims[n], kron_len(N, ranks, n), Y, ranks[n], fat_rule, U[n], pv);
+            st = orc_factor(dims[n], kron_len(N, ranks, n), Y, ranks[n], fat_rule, U[n], pv, NULL);
             if (st) { free(Y); return st; }
             if (n == N - 1) orc_core(dims[n], kron_len(N, ranks, n), ranks[n], Y, U[n], G);
         }

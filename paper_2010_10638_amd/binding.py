@@ -23,7 +23,7 @@ DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
 _STATUS = {1: "TK_ERR_ARG", 2: "TK_ERR_RANGE", 3: "TK_ERR_OOM", 4: "TK_ERR_HIP", 5: "TK_ERR_UNSUPPORTED"}
 
 EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "svd_update",
-           "tucker_svd_info", "core_fit",
+           "tucker_svd_info", "tucker_qrp_gaps", "core_fit",
            "hooi_sweep", "hooi_run", "reconstruct", "ttmc_adjoint", "tucker_profile", "tucker_profile_read", "tucker_free",
            "tucker_last_error")
 
@@ -54,6 +54,7 @@ def load_library(path: str = LIB_PATH):
     lib.qrp_update.argtypes = [P, I, P, P, P, P]
     lib.svd_update.argtypes = [P, I, P, P, P]
     lib.tucker_svd_info.argtypes = [P, P]
+    lib.tucker_qrp_gaps.argtypes = [P, I, P]
     lib.core_fit.argtypes = [P, P, P, P, P, P]
     lib.hooi_sweep.argtypes = [P, P, P, P, P, P]
     lib.hooi_run.argtypes = [P, P, P, I, ctypes.c_double, P, P, P]
@@ -81,23 +82,34 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _dev(t: torch.Tensor, dtype, name: str):
+def _dev(t: torch.Tensor, dtype, name: str, shape=None, numel=None):
+    """Device pointer of a contiguous CUDA tensor of the given dtype.  shape / numel: what the
+    library will read or write through the pointer; a mismatch raises ValueError before any call
+    into the library (a wrong-sized buffer would otherwise be an out-of-bounds device access)."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if numel is not None and t.numel() != int(numel):
+        raise ValueError(f"{name} must hold {int(numel)} values, got {t.numel()}")
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _ptrs(mats, n, skip=None, name="U"):
+def _ptrs(mats, ctx, skip=None, name="U"):
+    """Host array of the N factor pointers; U[k] must be float64 I_k x R_k (U[skip] is not read)."""
+    n = ctx.order
+    if len(mats) != n:
+        raise ValueError(f"{name} must hold {n} factors")
     arr = (ctypes.c_void_p * n)()
     for k in range(n):
         if k == skip:
             arr[k] = None
             continue
-        arr[k] = _dev(mats[k], torch.float64, f"{name}[{k}]").value
+        arr[k] = _dev(mats[k], torch.float64, f"{name}[{k}]", shape=(ctx.dims[k], ctx.ranks[k])).value
     return arr
 
 
@@ -179,10 +191,9 @@ def tucker_get_csf(ctx: Ctx, mode: int) -> dict:
 def ttmc_mode(ctx: Ctx, mode: int, U, Y: torch.Tensor | None = None) -> torch.Tensor:
     if Y is None:
         Y = torch.empty((ctx.dims[mode], ctx.K(mode)), dtype=ctx.ytype, device="cuda")
-    yp = _dev(Y, ctx.ytype, "Y")
-    if tuple(Y.shape) != (ctx.dims[mode], ctx.K(mode)):
-        raise ValueError("Y has the wrong shape")
-    _check(load_library().ttmc_mode(ctx.handle, mode, _ptrs(U, ctx.order, skip=mode), yp, _stream()))
+    _mode_ok(ctx, mode)
+    yp = _dev(Y, ctx.ytype, "Y", shape=(ctx.dims[mode], ctx.K(mode)))
+    _check(load_library().ttmc_mode(ctx.handle, mode, _ptrs(U, ctx, skip=mode), yp, _stream()))
     return Y
 
 
@@ -192,17 +203,20 @@ def qrp_update(ctx: Ctx, mode: int, Y: torch.Tensor, U_out: torch.Tensor | None 
         U_out = torch.empty((ctx.dims[mode], ctx.ranks[mode]), dtype=torch.float64, device="cuda")
     if piv is None:
         piv = torch.empty(ctx.ranks[mode], dtype=torch.int32, device="cuda")
-    _check(load_library().qrp_update(ctx.handle, mode, _dev(Y, ctx.ytype, "Y"),
-                                     _dev(U_out, torch.float64, "U_out"), _dev(piv, torch.int32, "piv"),
-                                     _stream()))
+    _mode_ok(ctx, mode)
+    _check(load_library().qrp_update(ctx.handle, mode, _dev(Y, ctx.ytype, "Y", shape=(ctx.dims[mode], ctx.K(mode))),
+                                     _dev(U_out, torch.float64, "U_out", shape=(ctx.dims[mode], ctx.ranks[mode])),
+                                     _dev(piv, torch.int32, "piv", numel=ctx.ranks[mode]), _stream()))
     return U_out, piv
 
 
 def svd_update(ctx: Ctx, mode: int, Y: torch.Tensor, U_out: torch.Tensor | None = None):
     if U_out is None:
         U_out = torch.empty((ctx.dims[mode], ctx.ranks[mode]), dtype=torch.float64, device="cuda")
-    _check(load_library().svd_update(ctx.handle, mode, _dev(Y, ctx.ytype, "Y"),
-                                     _dev(U_out, torch.float64, "U_out"), _stream()))
+    _mode_ok(ctx, mode)
+    _check(load_library().svd_update(ctx.handle, mode, _dev(Y, ctx.ytype, "Y", shape=(ctx.dims[mode], ctx.K(mode))),
+                                     _dev(U_out, torch.float64, "U_out", shape=(ctx.dims[mode], ctx.ranks[mode])),
+                                     _stream()))
     return U_out
 
 
@@ -214,15 +228,25 @@ def svd_info(ctx: Ctx) -> int:
     return v.value
 
 
+def qrp_gaps(ctx: Ctx, mode: int):
+    """Relative pivot gaps of the mode's last QRP (list of R_mode floats; NaN: not recorded)."""
+    _mode_ok(ctx, mode)
+    g = (ctypes.c_double * ctx.ranks[mode])()
+    _check(load_library().tucker_qrp_gaps(ctx.handle, mode, g))
+    return [g[j] for j in range(ctx.ranks[mode])]
+
+
 def core_fit(ctx: Ctx, Y_last: torch.Tensor, U_last: torch.Tensor, G: torch.Tensor | None = None,
              fit: torch.Tensor | None = None):
     if G is None:
         G = torch.empty(ctx.ranks, dtype=torch.float64, device="cuda")
     if fit is None:
         fit = torch.empty(1, dtype=torch.float64, device="cuda")
-    _check(load_library().core_fit(ctx.handle, _dev(Y_last, ctx.ytype, "Y_last"),
-                                   _dev(U_last, torch.float64, "U_last"), _dev(G, torch.float64, "G"),
-                                   _dev(fit, torch.float64, "fit"), _stream()))
+    n = ctx.order - 1
+    _check(load_library().core_fit(ctx.handle, _dev(Y_last, ctx.ytype, "Y_last", shape=(ctx.dims[n], ctx.K(n))),
+                                   _dev(U_last, torch.float64, "U_last", shape=(ctx.dims[n], ctx.ranks[n])),
+                                   _dev(G, torch.float64, "G", numel=_prod(ctx.ranks)),
+                                   _dev(fit, torch.float64, "fit", numel=1), _stream()))
     return G, fit
 
 
@@ -235,8 +259,8 @@ def hooi_sweep(ctx: Ctx, U, G: torch.Tensor | None = None, fit: torch.Tensor | N
     if fit is None:
         fit = torch.empty(1, dtype=torch.float64, device="cuda")
     host = ctypes.c_double()
-    _check(load_library().hooi_sweep(ctx.handle, _ptrs(U, ctx.order), _dev(G, torch.float64, "G"),
-                                     _dev(fit, torch.float64, "fit"),
+    _check(load_library().hooi_sweep(ctx.handle, _ptrs(U, ctx), _dev(G, torch.float64, "G", numel=_prod(ctx.ranks)),
+                                     _dev(fit, torch.float64, "fit", numel=1),
                                      ctypes.byref(host) if sync_fit else None, _stream()))
     return G, (host.value if sync_fit else fit)
 
@@ -246,22 +270,25 @@ def hooi_run(ctx: Ctx, U, max_sweeps: int, tol: float, G: torch.Tensor | None = 
     (G, fits) with one fit per sweep run."""
     if G is None:
         G = torch.empty(ctx.ranks, dtype=torch.float64, device="cuda")
-    fits = (ctypes.c_double * max_sweeps)()
+    fits = (ctypes.c_double * max(int(max_sweeps), 1))()   # max_sweeps < 1 is the library's TK_ERR_ARG
     done = ctypes.c_int()
-    _check(load_library().hooi_run(ctx.handle, _ptrs(U, ctx.order), _dev(G, torch.float64, "G"), int(max_sweeps),
+    _check(load_library().hooi_run(ctx.handle, _ptrs(U, ctx), _dev(G, torch.float64, "G", numel=_prod(ctx.ranks)),
+                                   int(max_sweeps),
                                    float(tol), fits, ctypes.byref(done), _stream()))
     return G, [fits[i] for i in range(done.value)]
 
 
 def reconstruct(ctx: Ctx, G: torch.Tensor, U, coords: torch.Tensor, out: torch.Tensor | None = None):
+    if coords.dim() != 2 or coords.shape[0] != ctx.order:
+        raise ValueError(f"coords must be [{ctx.order}, m]")
     m = int(coords.shape[1])
     if out is None:
         out = torch.empty(m, dtype=torch.float64, device="cuda")
     if m == 0:
         return out
-    _check(load_library().reconstruct(ctx.handle, _dev(G, torch.float64, "G"), _ptrs(U, ctx.order), m,
-                                      _dev(coords, torch.int32, "coords"), _dev(out, torch.float64, "out"),
-                                      _stream()))
+    _check(load_library().reconstruct(ctx.handle, _dev(G, torch.float64, "G", numel=_prod(ctx.ranks)),
+                                      _ptrs(U, ctx), m, _dev(coords, torch.int32, "coords"),
+                                      _dev(out, torch.float64, "out", numel=m), _stream()))
     return out
 
 
@@ -284,13 +311,22 @@ def ttmc_adjoint(ctx: Ctx, G: torch.Tensor, U, loss=None, gG=None, gU=None):
     for k in range(N):
         if tuple(U[k].shape) != (ctx.dims[k], ctx.ranks[k]) or tuple(gU[k].shape) != (ctx.dims[k], ctx.ranks[k]):
             raise ValueError(f"U[{k}] / gU[{k}] must be {ctx.dims[k]} x {ctx.ranks[k]}")
+    if len(U) != N or len(gU) != N:
+        raise ValueError(f"U / gU must hold {N} factors")
     if G.numel() != gG.numel() or G.numel() != _prod(ctx.ranks):
         raise ValueError("G / gG must hold prod(ranks) values")
+    if loss.numel() != 1:
+        raise ValueError("loss must hold one value")
     up = (ctypes.c_void_p * N)(*[_dev(U[k], dt, f"U[{k}]").value for k in range(N)])
     gp = (ctypes.c_void_p * N)(*[_dev(gU[k], dt, f"gU[{k}]").value for k in range(N)])
     _check(lib.ttmc_adjoint(ctx.handle, DTYPES[ctx.dtype], _dev(G, dt, "G"), up, _dev(loss, dt, "loss"),
                             _dev(gG, dt, "gG"), gp, _stream()))
     return loss, gG, gU
+
+
+def _mode_ok(ctx: Ctx, mode: int):
+    if not 0 <= int(mode) < ctx.order:
+        raise ValueError(f"mode must be in [0, {ctx.order})")
 
 
 def _prod(xs):

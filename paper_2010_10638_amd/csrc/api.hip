@@ -65,7 +65,7 @@ void free_ctx(tk_ctx* c) {
             if (p) (void)hipFree(p);
         if (c->Ulp[m]) (void)hipFree(c->Ulp[m]);
     }
-    void* ws[] = {c->ws.y, c->ws.carry, c->ws.qrp, c->ws.qrp_int, c->ws.scal};
+    void* ws[] = {c->ws.y, c->ws.carry, c->ws.qrp, c->ws.qrp_int, c->ws.scal, c->qrp_gaps};
     for (void* p : ws)
         if (p) (void)hipFree(p);
     delete c;
@@ -142,8 +142,12 @@ int tucker_init(tk_ctx** out, int order, const int64_t* dims, const int32_t* ran
     // factor copies and workspaces
     size_t ybytes = 0, cbytes = 0, qbytes = core_workspace_bytes(c);
     int64_t maxn = 0;
+    // factor copies: 16 columns (a multiple of 16 above 16), except order >= 4 with every rank
+    // <= 8, whose fiber-factored TTMc gathers 8-column rows (half the bytes and cache footprint)
+    bool narrow = order >= 4;
+    for (int t = 0; t < order; ++t) narrow = narrow && ranks[t] <= 8;
     for (int t = 0; t < order; ++t) {
-        c->ldU[t] = pad_rank(ranks[t]);
+        c->ldU[t] = narrow ? 8 : pad_rank(ranks[t]);
         if ((st = dmalloc(&c->Ulp[t], (size_t)dims[t] * c->ldU[t] * dtype_size(dtype)))) { free_ctx(c); return st; }
         if ((st = fill_zero(c->Ulp[t], (size_t)dims[t] * c->ldU[t] * dtype_size(dtype), s))) { free_ctx(c); return st; }
         const ModeLayout& ml = c->mode[t];
@@ -158,10 +162,12 @@ int tucker_init(tk_ctx** out, int order, const int64_t* dims, const int32_t* ran
     c->ws.qrp_int_bytes = (size_t)(64 + maxn) * 4;
     if ((st = dmalloc(&c->ws.y, ybytes)) || (st = dmalloc(&c->ws.carry, cbytes)) ||
         (st = dmalloc((void**)&c->ws.qrp, qbytes)) || (st = dmalloc((void**)&c->ws.qrp_int, c->ws.qrp_int_bytes)) ||
-        (st = dmalloc((void**)&c->ws.scal, 16 * sizeof(double)))) {
+        (st = dmalloc((void**)&c->ws.scal, 16 * sizeof(double))) ||
+        (st = dmalloc((void**)&c->qrp_gaps, (size_t)order * kGramMaxR * sizeof(double)))) {
         free_ctx(c);
         return st;
     }
+    if ((st = fill_f64(c->qrp_gaps, (int64_t)order * kGramMaxR, NAN, s))) { free_ctx(c); return st; }
     // the QRP flag and the completion ticket of the Q1 Gram start at zero
     if ((st = fill_zero(c->ws.qrp_int, c->ws.qrp_int_bytes, s))) { free_ctx(c); return st; }
     hipError_t e = hipStreamSynchronize(s);
@@ -240,6 +246,22 @@ int svd_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, void* stream
     st = svd_run(ctx, mode, Y, U_out, s);
     ctx->last_stream = s;
     return st;
+}
+
+int tucker_qrp_gaps(tk_ctx* ctx, int mode, double* gaps) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (mode < 0 || mode >= ctx->N) return set_error(TK_ERR_ARG, "mode %d outside [0, %d)", mode, ctx->N);
+    if (!gaps) return set_error(TK_ERR_ARG, "gaps is null");
+    if ((st = pending_error())) return st;
+    hipStream_t s = ctx->last_stream;
+    const int R = ctx->ranks[mode];
+    const int n = std::min(R, kGramMaxR);
+    TK_HIP(hipMemcpyAsync(gaps, ctx->qrp_gaps + (size_t)mode * kGramMaxR, (size_t)n * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+    for (int j = n; j < R; ++j) gaps[j] = NAN;
+    return TK_OK;
 }
 
 int tucker_svd_info(const tk_ctx* ctx, int* outer_steps) {

@@ -160,6 +160,15 @@ __global__ void k_pad_scatter(const int32_t* __restrict__ h, const int32_t* __re
         idx_p[(int64_t)j * P + d] = v;
     }
     val_p[d] = val_u[q];
+    // the row's last nonzero also fills the row's padding: zero values at its own indices, so a
+    // pad continues the last fiber of the row and gathers a factor row that is already cached
+    if (q == (int64_t)ptr[s + 1] - 1) {
+        for (int64_t e = d + 1; e < (int64_t)pptr[s + 1]; ++e) {
+            for (int j = 0; j < nothers; ++j)
+                idx_p[(int64_t)j * P + e] = idx_u[(int64_t)j * D + q];
+            val_p[e] = ST(0);
+        }
+    }
 }
 
 template <typename ST>

@@ -15,6 +15,11 @@ __global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t words) {
         p[e] = 0u;
 }
 
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
 template <typename LT>
 __global__ void k_convert_factor(const double* __restrict__ U, int64_t I, int R, int ld, LT* __restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -127,6 +132,13 @@ int fill_zero(void* p, size_t bytes, hipStream_t s) {
     if (words == 0) return TK_OK;
     k_fill_zero<<<std::min<unsigned>(2048, cdiv(words, 256)), 256, 0, s>>>((uint32_t*)p, words);
     TK_LAUNCH_CHECK("k_fill_zero");
+    return TK_OK;
+}
+
+int fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return TK_OK;
+    k_fill_f64<<<cdiv(n, 256), 256, 0, s>>>(p, n, v);
+    TK_LAUNCH_CHECK("k_fill_f64");
     return TK_OK;
 }
 

@@ -54,8 +54,8 @@ inline size_t ytype_size(int dt) { return dt == TK_F64 ? 8 : 4; }
 
 // Per-mode sorted layout and the chunk walk of the TTMc kernels.
 // The sorted nonzeros of a mode are stored padded: row s occupies [pptr[s], pptr[s+1]), its
-// ptr[s+1]-ptr[s] nonzeros followed by zero-valued entries (index 0) up to a multiple of 4, so that
-// a 4-nonzero MFMA step never spans two rows.  Bit 31 of the first other-mode index marks the first
+// ptr[s+1]-ptr[s] nonzeros followed by zero-valued entries (at the indices of the row's last
+// nonzero) up to a multiple of 4, so that a 4-nonzero MFMA step never spans two rows.  Bit 31 of the first other-mode index marks the first
 // entry of every row (kFirstOfRow); readers mask it off.
 constexpr uint32_t kFirstOfRow = 0x80000000u;
 constexpr int32_t kIndexMask = 0x7fffffff;
@@ -96,6 +96,8 @@ struct Workspace {
     double* scal = nullptr;         // small device scalars (fit when the caller gives none)
 };
 
+// pivot gaps of the last QRP of each mode: [N][kGramMaxR] relative gaps (NaN: not recorded)
+
 // Completion (adjoint TTMc) workspace, allocated on the first ttmc_adjoint call
 struct CompletionWs {
     bool ready = false;
@@ -122,6 +124,7 @@ struct tk_ctx {
     void* Ulp[tk::kMaxOrder] = {};   // factor copies in TTMc precision, I_k x ldU[k]
     int ldU[tk::kMaxOrder] = {};
     tk::Workspace ws;
+    double* qrp_gaps = nullptr;      // [N * kGramMaxR] relative pivot gaps of each mode's last QRP
     tk::CompletionWs cws;
     // SVD factor update: rocBLAS handle and eigen-solver workspace (allocated on first use)
     void* rb = nullptr;
@@ -189,6 +192,7 @@ int export_layout(tk_ctx* ctx, int mode, int32_t* idx_out, void* val_out, hipStr
 // Conversions (core.hip)
 int convert_factor(tk_ctx* ctx, int k, const double* U, hipStream_t s);
 int fill_zero(void* p, size_t bytes, hipStream_t s);
+int fill_f64(double* p, int64_t n, double v, hipStream_t s);   // a kernel, not a memset (graph-safe)
 
 // TTMc (ttmc.hip): uses ctx->Ulp copies
 // ev_main (optional, [2]): events recorded on s around the main TTMc kernel (fix-up excluded);

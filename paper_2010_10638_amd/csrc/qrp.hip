@@ -121,10 +121,11 @@ __device__ inline int wave_min_i32(int v) {
 template <int RM>
 __global__ __launch_bounds__(1024) void k_pivchol_cols(const double* __restrict__ C, int n, int R,
                                                        double* __restrict__ R11, double* __restrict__ Rinv,
-                                                       int32_t* __restrict__ pivw, int32_t* __restrict__ flag) {
+                                                       int32_t* __restrict__ pivw, int32_t* __restrict__ flag,
+                                                       double* __restrict__ gaps) {
     constexpr int kNone = 0x7fffffff;
     extern __shared__ double Ls[];              // [RM][n], row i = L[i][*] by column id
-    __shared__ double s_v[2][16], s_d[2][16];
+    __shared__ double s_v[2][16], s_d[2][16], s_v2[2][16];
     __shared__ int s_p[2][16], s_c[2][16];
     __shared__ double s_mx[16];
     __shared__ int s_piv[RM];
@@ -151,6 +152,9 @@ __global__ __launch_bounds__(1024) void k_pivchol_cols(const double* __restrict_
         const double v = cand ? d : -INFINITY;
         const double mx = wave_max_f64(v);
         const int lp = wave_min_i32((cand && v == mx) ? pos : kNone);
+        // the wave's runner-up (equal to mx when the maximum is tied): the pivot gap of step j
+        const double mx2 = wave_max_f64((cand && pos != lp) ? v : -INFINITY);
+        if (lane == 0) s_v2[b][wid] = mx2;
         double touch = 0.0;
         if (lp != kNone) {
             const uint64_t h = __ballot(pos == lp);
@@ -167,10 +171,18 @@ __global__ __launch_bounds__(1024) void k_pivchol_cols(const double* __restrict_
         double bv = s_v[b][0];
         int bp = s_p[b][0], cs = s_c[b][0];
         double djj = s_d[b][0];
+        int kw = 0;
         for (int k = 1; k < nw; ++k) {
             const double v2 = s_v[b][k];
             const int p2 = s_p[b][k];
-            if (v2 > bv || (v2 == bv && p2 < bp)) { bv = v2; bp = p2; cs = s_c[b][k]; djj = s_d[b][k]; }
+            if (v2 > bv || (v2 == bv && p2 < bp)) { bv = v2; bp = p2; cs = s_c[b][k]; djj = s_d[b][k]; kw = k; }
+        }
+        if (tid == 0) {
+            // relative gap between the chosen squared trailing norm and the largest other one
+            double second = s_v2[b][kw];
+            for (int k = 0; k < nw; ++k)
+                if (k != kw) second = fmax(second, s_v[b][k]);
+            gaps[j] = (second == -INFINITY) ? 1.0 : (bv > 0.0 ? (bv - second) / bv : 0.0);
         }
         if (bp == kNone) {
             // no comparable candidate (NaN): position j stays; its column and diagonal
@@ -563,10 +575,10 @@ __device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ 
                                double* __restrict__ V, double* __restrict__ w,
                                double* __restrict__ beta_s, int32_t* __restrict__ perm,
                                double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
-                               int32_t* __restrict__ piv_out) {
+                               int32_t* __restrict__ piv_out, double* __restrict__ gaps) {
     __shared__ double red[16];
     __shared__ double part[16 * 64];
-    __shared__ double bestv;
+    __shared__ double bestv, secondv;
     __shared__ int pbest;
     const int tid = threadIdx.x, nt = blockDim.x;
     if (src)
@@ -575,7 +587,7 @@ __device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ 
     __syncthreads();
     for (int j = 0; j < R; ++j) {
         // trailing norms, exact recompute; first maximum (columns are met in ascending order)
-        if (tid == 0) { bestv = -1.0; pbest = n; }
+        if (tid == 0) { bestv = -1.0; secondv = -1.0; pbest = n; }
         __syncthreads();
         column_sums(j, m, j, n, part, [&](int64_t i, int c) { const double x = A[i * n + c]; return x * x; },
                     [&](int c, double v, bool valid) {
@@ -587,9 +599,17 @@ __device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ 
                             const int p2 = __shfl_xor(bp, o);
                             if (v2 > bv || (v2 == bv && p2 < bp)) { bv = v2; bp = p2; }
                         }
-                        if ((threadIdx.x & 63) == 0 && bv > bestv) { bestv = bv; pbest = bp; }
+                        // the block's runner-up (the pivot gap)
+                        double b2 = (valid && c != bp) ? v : -1.0;
+                        for (int o = 1; o < 64; o <<= 1) b2 = fmax(b2, __shfl_xor(b2, o));
+                        if ((threadIdx.x & 63) == 0) {
+                            if (bv > bestv) { secondv = fmax(bestv, b2); bestv = bv; pbest = bp; }
+                            else secondv = fmax(secondv, bv);
+                        }
                     });
         if (tid == 0) {
+            if (gaps)
+                gaps[j] = (secondv < 0.0) ? 1.0 : (bestv > 0.0 ? (bestv - secondv) / bestv : 0.0);
             if (pbest >= n) pbest = j;   // no comparable norm (NaN): keep the column in place
             const int p0 = pbest;
             int t = perm[j]; perm[j] = perm[p0]; perm[p0] = t;
@@ -666,8 +686,8 @@ __global__ __launch_bounds__(1024) void k_house_qrp(const YT* __restrict__ src, 
                                                     double* __restrict__ V, double* __restrict__ w,
                                                     double* __restrict__ beta_s, int32_t* __restrict__ perm,
                                                     double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
-                                                    int32_t* __restrict__ piv_out) {
-    house_qrp_body<YT, LT>(src, A, m, n, R, V, w, beta_s, perm, U, Ulp, ldlp, piv_out);
+                                                    int32_t* __restrict__ piv_out, double* __restrict__ gaps) {
+    house_qrp_body<YT, LT>(src, A, m, n, R, V, w, beta_s, perm, U, Ulp, ldlp, piv_out, gaps);
 }
 
 // U = Y[:, piv] M and its low-precision copy; ldlp consecutive threads share a row, one output
@@ -682,9 +702,10 @@ __global__ __launch_bounds__(1024) void k_form_u(const YT* __restrict__ Y, int64
                                                 double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
                                                 double* __restrict__ A, double* __restrict__ V,
                                                 double* __restrict__ wv, double* __restrict__ beta_s,
-                                                int32_t* __restrict__ perm, int32_t* __restrict__ piv_out) {
+                                                int32_t* __restrict__ perm, int32_t* __restrict__ piv_out,
+                                                double* __restrict__ gaps) {
     if (*flag) {
-        if (blockIdx.x == 0) house_qrp_body<YT, LT>(Y, A, m, n, R, V, wv, beta_s, perm, U, Ulp, ldlp, piv_out);
+        if (blockIdx.x == 0) house_qrp_body<YT, LT>(Y, A, m, n, R, V, wv, beta_s, perm, U, Ulp, ldlp, piv_out, gaps);
         return;
     }
     __shared__ double sM[32 * 32];
@@ -788,16 +809,21 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
         TK_LAUNCH_CHECK("k_gram_reduce");
         const size_t lsz = (size_t)p.n * p.R * sizeof(double);
         const unsigned nthr = (unsigned)std::max(64, (p.n + 63) / 64 * 64);
+        double* gaps = ctx->qrp_gaps + (size_t)mode * kGramMaxR;
         if (p.R <= 16 && (size_t)p.n * 16 * sizeof(double) <= 64 * 1024)
             k_pivchol_cols<16><<<1, nthr, (size_t)p.n * 16 * sizeof(double), s>>>(W + p.o_C, p.n, p.R, W + p.o_R11,
-                                                                              W + p.o_Rinv, pivw, flag);
+                                                                              W + p.o_Rinv, pivw, flag, gaps);
         else if (p.R <= 32 && (size_t)p.n * 32 * sizeof(double) <= 64 * 1024)
             k_pivchol_cols<32><<<1, nthr, (size_t)p.n * 32 * sizeof(double), s>>>(W + p.o_C, p.n, p.R, W + p.o_R11,
-                                                                              W + p.o_Rinv, pivw, flag);
-        else if (lsz <= 64 * 1024)
-            k_pivchol<true><<<1, nthr, lsz, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, W + p.o_R11, W + p.o_Rinv, pivw, flag);
-        else
-            k_pivchol<false><<<1, nthr, 0, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, W + p.o_R11, W + p.o_Rinv, pivw, flag);
+                                                                              W + p.o_Rinv, pivw, flag, gaps);
+        else {
+            // this route does not record pivot gaps
+            if (int st = fill_f64(gaps, kGramMaxR, NAN, s)) return st;
+            if (lsz <= 64 * 1024)
+                k_pivchol<true><<<1, nthr, lsz, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, W + p.o_R11, W + p.o_Rinv, pivw, flag);
+            else
+                k_pivchol<false><<<1, nthr, 0, s>>>(W + p.o_C, p.n, p.R, W + p.o_L, W + p.o_R11, W + p.o_Rinv, pivw, flag);
+        }
         TK_LAUNCH_CHECK("k_pivchol");
         k_q1_gram<YT><<<(unsigned)p.nblk2, 256, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_Rinv, W + p.o_part2);
         TK_LAUNCH_CHECK("k_q1_gram");
@@ -814,16 +840,23 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
         TK_LAUNCH_CHECK("k_qrp_finish");
         // U = Y[:, piv] M, or (flag set) the Householder fallback on Y in workgroup 0
         k_form_u<YT, LT><<<cdiv(p.m * ldlp, 1024), 1024, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_M, flag, U, Ulp, ldlp,
-                                                             W + p.o_A, W + p.o_V, W + p.o_w, W + p.o_beta, perm, piv);
+                                                             W + p.o_A, W + p.o_V, W + p.o_w, W + p.o_beta, perm, piv,
+                                                             gaps);
         TK_LAUNCH_CHECK("k_form_u");
         return TK_OK;
+    }
+    // Householder routes: gaps for the first kGramMaxR steps
+    double* hgaps = ctx->qrp_gaps + (size_t)mode * kGramMaxR;
+    if (p.R > kGramMaxR) {
+        if (int st = fill_f64(hgaps, kGramMaxR, NAN, s)) return st;
+        hgaps = nullptr;
     }
     if (p.route == 2) {
         k_syrk_rows<YT><<<cdiv(I * I, 256), 256, 0, s>>>(Y, (int)I, (int)K, W + p.o_A);
         TK_LAUNCH_CHECK("k_syrk_rows");
     }
     k_house_qrp<YT, LT><<<1, 1024, 0, s>>>(p.route == 2 ? nullptr : Y, W + p.o_A, p.m, p.n, p.R, W + p.o_V, W + p.o_w,
-                                           W + p.o_beta, perm, U, Ulp, ldlp, piv);
+                                           W + p.o_beta, perm, U, Ulp, ldlp, piv, hgaps);
     TK_LAUNCH_CHECK("k_house_qrp");
     return TK_OK;
 }

@@ -295,7 +295,7 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
             const int r = 4 * kq + v;
             if (r < Ra && m < Rb) dst[r * Rb + m] = acc[v];
         }
-        if (owner) zero_gaps_ids<float>(a, row, prev_id, id, lane);
+        if (owner && (id != prev_id + 1 || row == a.S - 1)) zero_gaps_ids<float>(a, row, prev_id, id, lane);
         prev_id = id;
     };
     auto stream_load = [&](int pstart, int& ra, int& rb, float& rx) {
@@ -381,15 +381,22 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
             for (int t = 0; t < 16; ++t)
                 if (t < nsteps) acc = Acc<float>::mfma(av[t], bv[t], acc);
         } else {
-            for (int t = 0; t < nsteps; ++t) {
-                if (((starts >> (4 * t)) & 1ull) && (p + 4 * t != q0)) {
-                    flush(s);
-                    ++s;
-                    acc = f4_t{0, 0, 0, 0};
+            // rows open inside the batch: every operand is read first, then the unrolled steps
+            // write a finished row out before the step that opens the next one
+            float av[16], bv[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) operand(t, av[t], bv[t]);
+            const uint64_t opens = starts & ~((p == q0) ? 1ull : 0ull);
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                if (t < nsteps) {
+                    if ((opens >> (4 * t)) & 1ull) {
+                        flush(s);
+                        ++s;
+                        acc = f4_t{0, 0, 0, 0};
+                    }
+                    acc = Acc<float>::mfma(av[t], bv[t], acc);
                 }
-                float av, bv;
-                operand(t, av, bv);
-                acc = Acc<float>::mfma(av, bv, acc);
             }
         }
         // 4. batch b+1's rows into the tile
@@ -496,10 +503,11 @@ __host__ __device__ constexpr int fiber_slot_words(int tw) {
     return tw * kFiberStride + 64 * RF + 64;
 }
 
-template <typename AT, typename ST, int NM1, int KSL, int RF>
+template <typename AT, typename ST, int NM1, int KSL, int RF, int LDC>
 __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
     extern __shared__ __align__(16) unsigned char fiber_lds[];
-    constexpr int NV = 16 * (int)sizeof(ST) / 16;   // 16-byte loads per padded (16-column) row
+    constexpr int NV = LDC * (int)sizeof(ST) / 16;  // 16-byte loads per factor row (LDC columns)
+    static_assert(RF <= LDC || LDC == 16, "fiber rows narrower than the staged tile");
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ch = blockIdx.x * 4 + w;
@@ -550,13 +558,22 @@ __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
         for (int t = 0; t < NM1; ++t) ix[t] = a.idx[(int64_t)t * a.nnz + qc];
         xv = load_as<AT, ST>(a.val, (int64_t)qc);
     };
+    // the fiber-mode row is read only by a nonzero that starts a fiber (the walk reads it there
+    // alone); last_f: fiber index of the previous batch's last nonzero (-1 at the chunk start)
+    int last_f = -1;
     auto load_rows = [&](const i4v ix) {
+        int prevf = __shfl_up(ix[NM1 - 1], 1);
+        if (lane == 0) prevf = last_f;
+        last_f = __builtin_amdgcn_readlane(ix[NM1 - 1], 63);
+        const bool fst = ix[0] < 0 || ix[NM1 - 1] != prevf;
 #pragma unroll
         for (int t = 0; t < NM1; ++t) {
             const int32_t it = (t == 0) ? (ix[0] & kIndexMask) : ix[t];
             const uint4* row = (const uint4*)((const ST*)a.F[t] + (int64_t)it * a.ld[t]);
+            if (t < NM1 - 1 || fst) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) raw[t][v] = row[v];
+                for (int v = 0; v < NV; ++v) raw[t][v] = row[v];
+            }
         }
     };
     auto fold = [&]() {
@@ -604,11 +621,12 @@ __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
                 const ST* vals = (const ST*)raw[t];
                 if (t == NM1 - 1) {
 #pragma unroll
-                    for (int r = 0; r < RF; ++r) Tuf[lane * RF + r] = (r < Rf) ? load_as<AT, ST>(vals, (int64_t)r) : AT(0);
+                    for (int r = 0; r < RF; ++r)
+                        Tuf[lane * RF + r] = (r < Rf && r < LDC) ? load_as<AT, ST>(vals, (int64_t)(r < LDC ? r : 0)) : AT(0);
                 } else {
                     const int R = f.Rin[kin], o = f.off[kin];
 #pragma unroll
-                    for (int r = 0; r < 16; ++r)
+                    for (int r = 0; r < LDC; ++r)
                         if (r < R) Tin[(o + r) * kFiberStride + lane] = load_as<AT, ST>(vals, (int64_t)r);
                     ++kin;
                 }
@@ -714,38 +732,44 @@ int launch_generic(const TtmcArgs& a, hipStream_t s) {
 }
 
 template <typename AT, typename ST, int NM1>
-int launch_fiber_typed(const TtmcArgs& a, const FiberArgs& f, hipStream_t s) {
+int launch_fiber_typed(const TtmcArgs& a, const FiberArgs& f, int ldc, hipStream_t s) {
     const unsigned grid = (unsigned)((a.nchunks + 3) / 4);
     const int ksl = (f.Ks + 63) / 64;
-#define TK_FIB(KSL, RF)                                                                        \
+#define TK_FIB(KSL, RF, LDC)                                                                   \
     {                                                                                          \
         const size_t lds = (size_t)4 * fiber_slot_words<AT, RF>(f.tw) * sizeof(AT);            \
-        k_ttmc_fiber<AT, ST, NM1, KSL, RF><<<grid, 256, lds, s>>>(a, f);                       \
+        k_ttmc_fiber<AT, ST, NM1, KSL, RF, LDC><<<grid, 256, lds, s>>>(a, f);                  \
         TK_LAUNCH_CHECK("k_ttmc_fiber");                                                       \
         return TK_OK;                                                                          \
     }
-    if (f.Rf <= 8) {
-        if (ksl <= 1) TK_FIB(1, 8)
-        if (ksl <= 2) TK_FIB(2, 8)
-        if (ksl <= 4) TK_FIB(4, 8)
-        TK_FIB(8, 8)
+    if (ldc == 8) {   // every rank <= 8: 8-column factor copies
+        if (ksl <= 1) TK_FIB(1, 8, 8)
+        if (ksl <= 2) TK_FIB(2, 8, 8)
+        if (ksl <= 4) TK_FIB(4, 8, 8)
+        TK_FIB(8, 8, 8)
     }
-    if (ksl <= 1) TK_FIB(1, 16)
-    if (ksl <= 2) TK_FIB(2, 16)
-    TK_FIB(4, 16)
+    if (f.Rf <= 8) {
+        if (ksl <= 1) TK_FIB(1, 8, 16)
+        if (ksl <= 2) TK_FIB(2, 8, 16)
+        if (ksl <= 4) TK_FIB(4, 8, 16)
+        TK_FIB(8, 8, 16)
+    }
+    if (ksl <= 1) TK_FIB(1, 16, 16)
+    if (ksl <= 2) TK_FIB(2, 16, 16)
+    TK_FIB(4, 16, 16)
 #undef TK_FIB
 }
 
 template <int NM1>
-int launch_fiber_n(int dtype, const TtmcArgs& a, const FiberArgs& f, hipStream_t s) {
-    if (dtype == TK_F64) return launch_fiber_typed<double, double, NM1>(a, f, s);
-    if (dtype == TK_F32) return launch_fiber_typed<float, float, NM1>(a, f, s);
-    return launch_fiber_typed<float, bf16_t, NM1>(a, f, s);
+int launch_fiber_n(int dtype, const TtmcArgs& a, const FiberArgs& f, int ldc, hipStream_t s) {
+    if (dtype == TK_F64) return launch_fiber_typed<double, double, NM1>(a, f, ldc, s);
+    if (dtype == TK_F32) return launch_fiber_typed<float, float, NM1>(a, f, ldc, s);
+    return launch_fiber_typed<float, bf16_t, NM1>(a, f, ldc, s);
 }
 
-int launch_fiber(int dtype, const TtmcArgs& a, const FiberArgs& f, hipStream_t s) {
-    if (a.nm1 == 3) return launch_fiber_n<3>(dtype, a, f, s);
-    return launch_fiber_n<4>(dtype, a, f, s);
+int launch_fiber(int dtype, const TtmcArgs& a, const FiberArgs& f, int ldc, hipStream_t s) {
+    if (a.nm1 == 3) return launch_fiber_n<3>(dtype, a, f, ldc, s);
+    return launch_fiber_n<4>(dtype, a, f, ldc, s);
 }
 
 }  // namespace
@@ -783,7 +807,10 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
         a.F[j] = ctx->Ulp[t];
         a.ld[j] = ctx->ldU[t];
         a.R[j] = ctx->ranks[t];
-        mfma_ok = mfma_ok && a.R[j] <= 16 && a.ld[j] == 16;
+        // the order-3 kernels form gather offsets in 32 bits (byte offsets in k_ttmc3_lds,
+        // element offsets in int in k_ttmc3_mfma): only factors below 2^31 bytes take them
+        const bool off32 = (uint64_t)ctx->dims[t] * (uint64_t)a.ld[j] * dtype_size(ctx->dtype) < (1ull << 31);
+        mfma_ok = mfma_ok && a.R[j] <= 16 && a.ld[j] == 16 && off32;
     }
     const unsigned grid = (unsigned)((ml.nchunks + 3) / 4);
     int st = TK_OK;
@@ -804,7 +831,9 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
         }
         fa.Rf = a.R[N - 2];
         fa.tw = off;
-        fiber_ok = small && (N == 4 || N == 5) && off <= kFiberTile &&
+        bool ld_ok = true;
+        for (int j = 0; j < N - 1; ++j) ld_ok = ld_ok && (a.ld[j] == 8 || a.ld[j] == 16);
+        fiber_ok = small && ld_ok && (N == 4 || N == 5) && off <= kFiberTile &&
                    ((fa.Rf <= 8 && fa.Ks <= 64 * 8) || (fa.Rf <= 16 && fa.Ks <= 64 * 4));
     }
     if (ev_main) TK_HIP(hipEventRecord(ev_main[0], s));
@@ -820,7 +849,10 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
             TK_LAUNCH_CHECK("k_ttmc3_lds");
         }
     } else if (fiber_ok) {
-        st = launch_fiber(ctx->dtype, a, fa, s);
+        // factor copies of 8 columns (every rank <= 8) or 16
+        int ldc = 8;
+        for (int j = 0; j < N - 1; ++j) ldc = (a.ld[j] == 8) ? ldc : 16;
+        st = launch_fiber(ctx->dtype, a, fa, ldc, s);
         if (st) return st;
     } else {
         if (ctx->dtype == TK_F64) st = launch_generic<double, double>(a, s);

@@ -189,6 +189,59 @@ def test_ttmc_long_rows(tk, dtype):
     assert np.all(Y[lens == 0] == 0)
 
 
+def fibered_case(seed, dims, ranks, nnz, fibers_per_row, a=1.2):
+    """Order-3 nonzeros whose rows (Zipf-distributed lengths) draw their first other-mode index
+    from a few values per row, so that fibers (i_n, i_f) hold many nonzeros, next to rows of one
+    to three nonzeros (the structure of the recommendation-shaped workload)."""
+    rng = np.random.default_rng(seed)
+    i0 = synth.zipf_index(rng, dims[0], a, 3 * nnz)
+    fsel = rng.integers(0, fibers_per_row, size=i0.size)
+    i1 = (i0 * 7919 + fsel * 104729) % dims[1]
+    i2 = rng.integers(0, dims[2], size=i0.size)
+    key = (i0 * dims[1] + i1) * dims[2] + i2
+    _, first = np.unique(key, return_index=True)
+    first = np.sort(first)[:nnz]
+    coords = np.stack([i0[first], i1[first], i2[first]]).astype(np.int32)
+    vals = np.exp(rng.standard_normal(coords.shape[1]))
+    U = [synth.gaussian_qr(rng, d, r) for d, r in zip(dims, ranks)]
+    return coords, vals, U
+
+
+TTMC3_KERNEL_CASES = [
+    # dims, ranks, nnz, fibers per row
+    ([3000, 400, 300], [10, 10, 10], 60000, 3),    # long fibers, Zipf rows (hot rows split over chunks)
+    ([5000, 300, 200], [16, 16, 16], 40000, 2),    # full 16 x 16 tiles
+    ([2000, 500, 90], [7, 12, 5], 30000, 5),       # R_f != R_in, odd ranks
+    ([800, 60, 700], [4, 12, 3], 25000, 1),        # one fiber per row in mode 0
+    ([9000, 9000, 50], [10, 10, 10], 20000, 40),   # mostly short rows and one-nonzero fibers
+]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("case", range(len(TTMC3_KERNEL_CASES)))
+def test_ttmc3_skewed_rows_and_fibers(tk, dtype, case):
+    """The order-3 MFMA kernel against the oracle on every mode, on Zipf-shaped tensors with long
+    and short fibers, hot rows cut across pieces next to one-nonzero rows, and several rows opening
+    inside one batch; deterministic across calls; empty rows are zero."""
+    dims, ranks, nnz, fpr = TTMC3_KERNEL_CASES[case]
+    coords, vals, U = fibered_case(200 + case, dims, ranks, nnz, fpr)
+    ctx = tk.tucker_init(*to_dev(coords, vals), dims, ranks, dtype=dtype)
+    Ud = dev_list(U)
+    for mode in range(3):
+        Yt = tk.ttmc_mode(ctx, mode, Ud)
+        assert torch.equal(Yt, tk.ttmc_mode(ctx, mode, Ud))
+        Y = Yt.double().cpu().numpy()
+        Yo = oracle.ttmc(coords, vals, dims, ranks, mode, U)
+        assert rel_fro(Y, Yo) <= TOL_Y[dtype], (mode, rel_fro(Y, Yo))
+        Yc = oracle.ttmc(coords, cast_vals(vals, dtype), dims, ranks, mode, cast_inputs(U, dtype))
+        assert rel_fro(Y, Yc) <= 2e-6, (mode, rel_fro(Y, Yc))
+        lens = np.bincount(coords[mode], minlength=dims[mode])
+        assert np.all(Y[lens == 0] == 0)
+        rows = np.flatnonzero(lens)
+        worst = max(rel_fro(Y[i], Yc[i]) for i in rows[:: max(1, rows.size // 200)])
+        assert worst <= 2e-5, (mode, worst)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_ttmc_degenerate(tk, dtype):
     # a single nonzero; all nonzeros in one row; rank-1 factors
@@ -295,6 +348,44 @@ def test_qrp_tied_norms(tk, K):
     assert pe[0] == 3
     assert piv.cpu().numpy().tolist() == pe.tolist()
     np.testing.assert_allclose(U.cpu().numpy(), Ue, atol=1e-10)
+
+
+@pytest.mark.parametrize("K,R", [(64, 12), (256, 16), (192, 24)])
+def test_qrp_pivot_gaps(tk, K, R):
+    """tucker_qrp_gaps after qrp_update equals the oracle's per-step gaps on the same Y (a near
+    tie included); a tie gives 0; the fat-matrix route (Householder on Y Y^T) records the gaps of
+    that matrix; the global-memory Cholesky route (K * 32 doubles above 64 KB) and a mode without
+    a QRP give NaN."""
+    rng = np.random.default_rng(K + R)
+    dims, ranks = [2000, 8, K // 8], [R, 8, K // 8]
+    w = synth.small_uniform(9, dims, ranks, 100)
+    ctx = make(tk, w, "f64")
+    assert all(np.isnan(tk.qrp_gaps(ctx, 1)))
+    Y = rng.standard_normal((2000, K)) * np.linspace(1.0, 2.0, K)
+    Y[:, 5] = Y[:, 2] * (1.0 + 1e-7)
+    _, piv = tk.qrp_update(ctx, 0, torch.from_numpy(Y).cuda())
+    g = tk.qrp_gaps(ctx, 0)
+    _, pe, ge = oracle.factor(Y, R, gaps=True)
+    assert piv.cpu().tolist() == pe.tolist()
+    np.testing.assert_allclose(g, ge, atol=1e-10)
+    Y[:, 7] = Y[:, K - 1]
+    Y[::2, 7] *= -1.0
+    Y[:, K - 1] *= 5.0
+    Y[:, 7] *= 5.0
+    tk.qrp_update(ctx, 0, torch.from_numpy(Y).cuda())
+    assert tk.qrp_gaps(ctx, 0)[0] <= 1e-15
+    # the fat-matrix route: Householder QRP of Y Y^T
+    wf = synth.small_uniform(10, [20, 30, 30], [5, 6, 6], 2000)
+    ctxf = make(tk, wf, "f64")
+    Yf = rng.standard_normal((20, 36))
+    _, pf = tk.qrp_update(ctxf, 0, torch.from_numpy(Yf).cuda())
+    _, pfe, gfe = oracle.factor(Yf, 5, gaps=True)
+    assert pf.cpu().tolist() == pfe.tolist()
+    np.testing.assert_allclose(tk.qrp_gaps(ctxf, 0), gfe, atol=1e-10)
+    wl = synth.small_uniform(11, [2000, 8, 40], [24, 8, 40], 100)
+    ctxl = make(tk, wl, "f64")
+    _, pl = tk.qrp_update(ctxl, 0, torch.from_numpy(rng.standard_normal((2000, 320))).cuda())
+    assert all(np.isnan(tk.qrp_gaps(ctxl, 0)))
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

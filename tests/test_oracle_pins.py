@@ -92,6 +92,25 @@ def test_ttmc_linear_and_duplicates():
     np.testing.assert_allclose(oracle.ttmc(cc, cv, w.dims, w.ranks, 1, w.U_init), Y1, atol=1e-13)
 
 
+@pytest.mark.parametrize("threads", [2, 3, 8, 64])
+def test_ttmc_threads_bit_identical(threads):
+    """The host-threaded TTMc (CPU-baseline timing) gives exactly orc_ttmc's result in every mode,
+    including more threads than non-empty rows and a skewed row distribution; the threaded sweep
+    gives the same fits and factors."""
+    w = random_tensor(14, [40, 30, 9], 3000, [4, 3, 5])
+    c = w.coords.copy()
+    c[0, : 1500] = 3                              # one hot row holding half the nonzeros
+    cc, cv = oracle.coalesce(c, w.vals, w.dims)
+    for n in range(3):
+        Y1 = oracle.ttmc(cc, cv, w.dims, w.ranks, n, w.U_init)
+        Yt = oracle.ttmc(cc, cv, w.dims, w.ranks, n, w.U_init, threads=threads)
+        assert np.array_equal(Y1, Yt)
+    U1, G1, f1, p1 = oracle.hooi(cc, cv, w.dims, w.ranks, w.U_init, 2)
+    Ut, Gt, ft, pt = oracle.hooi(cc, cv, w.dims, w.ranks, w.U_init, 2, threads=threads)
+    assert np.array_equal(f1, ft) and np.array_equal(G1, Gt) and np.array_equal(p1, pt)
+    assert all(np.array_equal(a, b) for a, b in zip(U1, Ut))
+
+
 # ------------------------------------------------------------------------------------------
 # QRP
 # ------------------------------------------------------------------------------------------
@@ -110,6 +129,27 @@ def test_qrp_matches_lapack(m, n, R):
     for j in range(R):
         s = 1.0 if (j < m - 1) else np.sign(Q[:, j] @ Ql[:, j])
         np.testing.assert_allclose(Q[:, j], s * Ql[:, j], atol=1e-12)
+
+
+def test_qrp_pivot_gaps_from_projections():
+    """The oracle's per-step pivot gaps equal those from the definition: at step j the trailing
+    squared norm of column c is ||a_c||^2 - ||Q_j^T a_c||^2 with Q_j the first j columns of Q (LAPACK
+    pivoted QR); the gap is (largest - second largest) / largest over the columns not yet chosen."""
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((200, 24)) * np.linspace(1.0, 3.0, 24)
+    A[:, 7] = A[:, 3] * 1.0000001            # a near tie
+    R = 10
+    _, piv, gaps = oracle.qrp(A, R, gaps=True)
+    Q, _, P = scipy.linalg.qr(A, pivoting=True, mode="economic")
+    assert piv.tolist() == P[:R].tolist()
+    chosen = []
+    for j in range(R):
+        Qj = Q[:, :j]
+        norms = (A * A).sum(axis=0) - ((Qj.T @ A) ** 2).sum(axis=0)
+        cand = np.array([c for c in range(A.shape[1]) if c not in chosen])
+        v = np.sort(norms[cand])[::-1]
+        assert abs(gaps[j] - (v[0] - v[1]) / v[0]) <= 1e-9, j
+        chosen.append(P[j])
 
 
 def test_qrp_invariants():
