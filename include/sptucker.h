@@ -182,6 +182,23 @@ int core_fit(tk_ctx* ctx, const void* Y_last, const double* U_last, double* G, d
              void* stream);
 
 /*
+ * core_fit_static - core_fit without a context and without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arithmetic and kernels as core_fit; the slab partials live in a static
+ * per-device scratch array of the library (8 MiB per device, held until the process ends).
+ *   ytype   TK_F64 or TK_F32: element type of Y_last
+ *   I, R, K I_N, R_N, K_N; R * K must not exceed 2^20 (else TK_ERR_UNSUPPORTED, nothing launched)
+ *   Y_last  device I x K (ytype), U_last device double I x R, G device double[R * K] (C-order as
+ *           for core_fit), fit device double scalar or NULL, normx2 = ||X||^2 (host value)
+ * Calls on the same device share the scratch: calls that overlap in time on one device (two
+ * streams, two host threads) race and must be serialised by the caller.  Nothing in the scratch
+ * needs clearing: every call overwrites the partials it reads.  Errors: TK_ERR_ARG,
+ * TK_ERR_UNSUPPORTED, TK_ERR_HIP.
+ */
+int core_fit_static(int ytype, int64_t I, int32_t R, int64_t K, const void* Y_last, const double* U_last,
+                    double normx2, double* G, double* fit, void* stream);
+
+/*
  * hooi_sweep - one sweep of Alg. 2: for n = 0..N-1, TTMc with the current factors then
  * U_n <- QRP(Y_(n), R_n) (modes updated in order, each using the factors already refreshed in this
  * sweep); then the core and the fit.  A context created with TK_FLAG_SVD updates the factors with

@@ -23,7 +23,7 @@ DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
 _STATUS = {1: "TK_ERR_ARG", 2: "TK_ERR_RANGE", 3: "TK_ERR_OOM", 4: "TK_ERR_HIP", 5: "TK_ERR_UNSUPPORTED"}
 
 EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "svd_update",
-           "tucker_svd_info", "tucker_qrp_gaps", "core_fit",
+           "tucker_svd_info", "tucker_qrp_gaps", "core_fit", "core_fit_static",
            "hooi_sweep", "hooi_run", "reconstruct", "ttmc_adjoint", "tucker_profile", "tucker_profile_read", "tucker_free",
            "tucker_last_error")
 
@@ -56,6 +56,7 @@ def load_library(path: str = LIB_PATH):
     lib.tucker_svd_info.argtypes = [P, P]
     lib.tucker_qrp_gaps.argtypes = [P, I, P]
     lib.core_fit.argtypes = [P, P, P, P, P, P]
+    lib.core_fit_static.argtypes = [I, I64, ctypes.c_int32, I64, P, P, ctypes.c_double, P, P, P]
     lib.hooi_sweep.argtypes = [P, P, P, P, P, P]
     lib.hooi_run.argtypes = [P, P, P, I, ctypes.c_double, P, P, P]
     lib.reconstruct.argtypes = [P, P, P, I64, P, P, P]
@@ -247,6 +248,28 @@ def core_fit(ctx: Ctx, Y_last: torch.Tensor, U_last: torch.Tensor, G: torch.Tens
                                    _dev(U_last, torch.float64, "U_last", shape=(ctx.dims[n], ctx.ranks[n])),
                                    _dev(G, torch.float64, "G", numel=_prod(ctx.ranks)),
                                    _dev(fit, torch.float64, "fit", numel=1), _stream()))
+    return G, fit
+
+
+def core_fit_static(Y_last: torch.Tensor, U_last: torch.Tensor, normx2: float, G: torch.Tensor | None = None,
+                    fit: torch.Tensor | None = None):
+    """core_fit without a context or allocation (static per-device scratch).  Y_last: I x K float32
+    or float64; U_last: I x R float64; G: R * K float64 values (C-order as core_fit's)."""
+    if Y_last.dim() != 2 or U_last.dim() != 2 or Y_last.shape[0] != U_last.shape[0]:
+        raise ValueError("Y_last must be I x K and U_last I x R")
+    I, K = (int(x) for x in Y_last.shape)
+    R = int(U_last.shape[1])
+    ytype = {torch.float64: TK_F64, torch.float32: TK_F32}.get(Y_last.dtype)
+    if ytype is None:
+        raise TypeError("Y_last must be float32 or float64")
+    if G is None:
+        G = torch.empty(R * K, dtype=torch.float64, device="cuda")
+    if fit is None:
+        fit = torch.empty(1, dtype=torch.float64, device="cuda")
+    _check(load_library().core_fit_static(ytype, I, R, K, _dev(Y_last, Y_last.dtype, "Y_last"),
+                                          _dev(U_last, torch.float64, "U_last"), float(normx2),
+                                          _dev(G, torch.float64, "G", numel=R * K), _dev(fit, torch.float64, "fit", numel=1),
+                                          _stream()))
     return G, fit
 
 

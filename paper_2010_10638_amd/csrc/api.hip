@@ -283,6 +283,20 @@ int core_fit(tk_ctx* ctx, const void* Y_last, const double* U_last, double* G, d
     return st;
 }
 
+int core_fit_static(int ytype, int64_t I, int32_t R, int64_t K, const void* Y_last, const double* U_last,
+                    double normx2, double* G, double* fit, void* stream) {
+    if (ytype != TK_F64 && ytype != TK_F32) return set_error(TK_ERR_ARG, "ytype must be TK_F64 or TK_F32");
+    if (I < 1 || R < 1 || K < 1) return set_error(TK_ERR_ARG, "I, R and K must be positive");
+    if (!Y_last || !U_last || !G) return set_error(TK_ERR_ARG, "Y_last/U_last/G is null");
+    if (!(normx2 >= 0.0) || !std::isfinite(normx2)) return set_error(TK_ERR_ARG, "normx2 must be finite and >= 0");
+    if ((int64_t)R * K > core_static_max_cols())
+        return set_error(TK_ERR_UNSUPPORTED, "R * K = %lld exceeds the static scratch of %lld doubles",
+                         (long long)((int64_t)R * K), (long long)core_static_max_cols());
+    int st = pending_error();
+    if (st) return st;
+    return core_static_run(ytype, I, R, K, Y_last, U_last, normx2, G, fit, (hipStream_t)stream);
+}
+
 int hooi_sweep(tk_ctx* ctx, double* const* U, double* G, double* fit_dev, double* fit_host, void* stream) {
     int st = check_ctx(ctx);
     if (st) return st;

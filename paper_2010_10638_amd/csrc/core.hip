@@ -1,9 +1,16 @@
 // Core tensor and fit (paper Alg. 2, the step after the mode loop; Sec. III-B unfolded form
 // G_(N) = U_N^T Y_(N)), sampled reconstruction of the Tucker model, factor conversions.
+#include <mutex>
+
 #include "internal.h"
 #include "atb.h"
 
 namespace tk {
+
+// Scratch of the allocation-free core/fit entry point (core_fit_static): the per-slab partial
+// products of G_(N).  One copy per device, held until the process ends; calls on one device share it.
+constexpr int64_t kCoreScratchDoubles = (int64_t)1 << 20;   // 8 MiB
+static __device__ __align__(256) double scratch[kCoreScratchDoubles];
 
 namespace {
 
@@ -190,6 +197,53 @@ int core_run(tk_ctx* ctx, const void* Y, const double* U, double* G, double* fit
     TK_LAUNCH_CHECK("k_core_reduce");
     if (fit) {
         k_core_fit<<<1, 1024, 0, s>>>(G, (int64_t)K * R, ctx->normx2, fit);
+        TK_LAUNCH_CHECK("k_core_fit");
+    }
+    return TK_OK;
+}
+
+int64_t core_static_max_cols() { return kCoreScratchDoubles; }
+
+// Device address of this device's copy of `scratch`, looked up once per device with that device
+// current (the array's name is only a host-side stand-in).
+static int core_scratch_address(double** out) {
+    static std::mutex mu;
+    static double* addr[64] = {};
+    int dev = 0;
+    TK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(TK_ERR_UNSUPPORTED, "device ordinal %d above 63", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        TK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_error(TK_ERR_HIP, "hipGetSymbolAddress returned a null address");
+        addr[dev] = (double*)p;
+    }
+    *out = addr[dev];
+    return TK_OK;
+}
+
+int core_static_run(int ytype, int64_t I, int R, int64_t K, const void* Y, const double* U, double normx2,
+                    double* G, double* fit, hipStream_t s) {
+    double* part = nullptr;
+    int st = core_scratch_address(&part);
+    if (st) return st;
+    // slabs as in core_run, at most as many as the scratch holds
+    const int64_t cblocks = ((K + 63) / 64) * ((R + 63) / 64);
+    int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(cblocks, 1), (I + 127) / 128));
+    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, kCoreScratchDoubles / ((int64_t)R * K)));
+    const int64_t slab = ((I + nsplit - 1) / nsplit + 31) / 32 * 32;
+    nsplit = (I + slab - 1) / slab;
+    dim3 grid(cdiv(K, 64), (unsigned)nsplit, cdiv(R, 64));
+    if (ytype == TK_F64)
+        k_core_partial<double><<<grid, 256, 0, s>>>((const double*)Y, U, I, (int)K, R, slab, part);
+    else
+        k_core_partial<float><<<grid, 256, 0, s>>>((const float*)Y, U, I, (int)K, R, slab, part);
+    TK_LAUNCH_CHECK("k_core_partial");
+    k_core_reduce<<<cdiv(K * R, 256), 256, 0, s>>>(part, (int)nsplit, (int)K, R, G);
+    TK_LAUNCH_CHECK("k_core_reduce");
+    if (fit) {
+        k_core_fit<<<1, 1024, 0, s>>>(G, K * R, normx2, fit);
         TK_LAUNCH_CHECK("k_core_fit");
     }
     return TK_OK;

@@ -218,6 +218,10 @@ int qrp_route(const tk_ctx* ctx, int mode);
 // Core, fit, reconstruct (core.hip)
 int core_run(tk_ctx* ctx, const void* Y, const double* U, double* G, double* fit, hipStream_t s);
 size_t core_workspace_bytes(const tk_ctx* ctx);
+// allocation-free core and fit on the library's static per-device scratch (R * K <= the returned bound)
+int core_static_run(int ytype, int64_t I, int R, int64_t K, const void* Y, const double* U, double normx2,
+                    double* G, double* fit, hipStream_t s);
+int64_t core_static_max_cols();
 int reconstruct_run(tk_ctx* ctx, const double* G, const double* const* U, int64_t m,
                     const int32_t* coords, double* out, hipStream_t s);
 
