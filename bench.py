@@ -397,10 +397,11 @@ def main():
     ap.add_argument("--small", action="store_true", help="small tensor (for profiling dry runs)")
     ap.add_argument("--workload", default="skewed-f32",
                     choices=["skewed-f32", "skewed-bf16", "lowrank", "hooi200", "order4-f32", "order4-bf16",
-                             "completion"],
+                             "image", "completion"],
                     help="skewed-* (default FP32): 500,000 x 100,000 x 365, 50M Zipf nnz, R 10; lowrank: "
                     "10,000^3, 10M nnz, R 16, FP32 TTMc; hooi200: 200^3, 20,000 nnz, R 8, FP64; order4-*: "
-                    "50,000 x 50,000 x 5,000 x 100, 20M nnz, R 8; completion: 100,000 x 100,000 x 1,000, "
+                    "50,000 x 50,000 x 5,000 x 100, 20M nnz, R 8; image: order 2, 130 x 150 image-shaped, R 30, "
+                    "FP64; completion: 100,000 x 100,000 x 1,000, "
                     "30M entries, R 16, one Adam step of the completion loss per step")
     ap.add_argument("--factor", default="qrp", choices=["qrp", "svd"],
                     help="factor update of the HOOI sweeps: qrp (Alg. 2, default) or svd (Alg. 1, the "
@@ -454,6 +455,8 @@ def main():
         w = synth.skewed(dtype=args.workload.split("-")[1])
     elif args.workload.startswith("order4"):
         w = synth.order4(dtype=args.workload.split("-")[1])
+    elif args.workload == "image":
+        w = synth.image_like()
     else:
         w = synth.completion()
     print(f"# generated {w.name} in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)

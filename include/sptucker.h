@@ -159,6 +159,23 @@ int svd_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, void* stream
  */
 int tucker_svd_info(const tk_ctx* ctx, int* outer_steps);
 
+/* The TTMc kernel a mode runs (tucker_ttmc_kernel). */
+enum tk_ttmc_kernel {
+    TK_TTMC_GENERIC = 0,   /* any order and K_n <= TK_MAX_KCOLS, vector ALU */
+    TK_TTMC_ORDER3 = 1,    /* order 3, other ranks <= 16, factors below 2^31 bytes: matrix cores */
+    TK_TTMC_FIBER = 2      /* order 4-5: fiber-factored (each fiber's row of the last other mode once) */
+};
+
+/*
+ * tucker_ttmc_kernel - which TTMc kernel ttmc_mode / hooi_sweep run for a mode of a tensor of this
+ * shape (host-only: no device, no context).  The order-3 matrix-core kernel forms its gather
+ * offsets in 32 bits, so it is taken only while every other factor's copy stays below 2^31 bytes
+ * (dims[t] x 16 columns x the TTMc type's size); larger factors take the generic kernel.
+ *   kernel  host int, receives enum tk_ttmc_kernel
+ * Errors: TK_ERR_ARG.
+ */
+int tucker_ttmc_kernel(int order, const int64_t* dims, const int32_t* ranks, int dtype, int mode, int* kernel);
+
 /*
  * tucker_qrp_gaps - pivot gaps of the last QRP of a mode (qrp_update or a sweep): gaps[j] =
  * (d_j - d'_j) / d_j, where d_j is the squared norm of the trailing column chosen at step j of the
@@ -197,6 +214,22 @@ int core_fit(tk_ctx* ctx, const void* Y_last, const double* U_last, double* G, d
  */
 int core_fit_static(int ytype, int64_t I, int32_t R, int64_t K, const void* Y_last, const double* U_last,
                     double normx2, double* G, double* fit, void* stream);
+
+/*
+ * hosvd_init - HOSVD-style initial factors (Alg. 1 starts HOOI from the leading left singular
+ * vectors of every unfolding X_(n)), computed on a sketch: for each mode n independently,
+ * Y_(n) = X_(n) (kron_{k != n} Omega_k) with the caller's random test factors Omega_k (a
+ * Kronecker-structured random projection of the columns of X_(n), the TTMc of ttmc_mode), then
+ * U_n <- QRP(Y_(n), R_n) (use_svd = 0, the factor update of Alg. 2) or its leading R_n left
+ * singular vectors (use_svd != 0, as svd_update).  With Omega_k of full column rank the sketch
+ * keeps the column space of X_(n) whenever rank(X_(n)) <= K_n.
+ *   Omega  host array of N device pointers to double I_k x R_k (e.g. Gaussian; read only; Omega[n]
+ *          is read for the other modes)
+ *   U_out  host array of N device pointers to double I_k x R_k, written (must not alias Omega)
+ * The context's factor copies and Y buffer are overwritten.  Errors: as ttmc_mode and
+ * qrp_update / svd_update.
+ */
+int hosvd_init(tk_ctx* ctx, const double* const* Omega, double* const* U_out, int use_svd, void* stream);
 
 /*
  * hooi_sweep - one sweep of Alg. 2: for n = 0..N-1, TTMc with the current factors then

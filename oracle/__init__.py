@@ -257,6 +257,17 @@ def svd_factor(Y, R: int) -> np.ndarray:
     return np.ascontiguousarray(u[:, :R])
 
 
+def hosvd_sketch(coords, vals, dims, ranks, Omega, svd: bool = False):
+    """HOSVD-style initial factors (Alg. 1's start) from a sketch: for each mode n independently,
+    Y = X_(n) (kron_{k != n} Omega_k) by the TTMc, then U_n = QRP(Y, R_n) (the factor update of
+    Alg. 2) or the leading R_n left singular vectors of Y (LAPACK)."""
+    out = []
+    for n in range(len(dims)):
+        Y = ttmc(coords, vals, dims, ranks, n, Omega)
+        out.append(svd_factor(Y, int(ranks[n])) if svd else factor(Y, int(ranks[n]))[0])
+    return out
+
+
 def hooi_svd(coords, vals, dims, ranks, U_init, sweeps: int):
     """Alg. 2 sweeps with the QRP replaced by the SVD of Alg. 1.  Returns (U, G, fits)."""
     U = [np.array(u, dtype=np.float64, copy=True) for u in U_init]

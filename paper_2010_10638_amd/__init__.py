@@ -4,7 +4,7 @@ The computation lives in the HIP library ``lib/libsptucker.so`` (C ABI: include/
 ``binding`` marshals torch tensors into it.
 """
 from .binding import (  # noqa: F401
-    EXPORTS, LIB_PATH, TuckerError, core_fit, core_fit_static, hooi_run, hooi_sweep, load_library, qrp_gaps, qrp_update, reconstruct, svd_info, svd_update,
+    EXPORTS, LIB_PATH, TuckerError, core_fit, core_fit_static, hosvd_init, hooi_run, hooi_sweep, load_library, qrp_gaps, qrp_update, reconstruct, ttmc_kernel, svd_info, svd_update,
     ttmc_adjoint, ttmc_mode, tucker_free, tucker_profile, tucker_profile_read, tucker_get_csf, tucker_get_info,
     tucker_init,
 )

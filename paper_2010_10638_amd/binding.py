@@ -23,8 +23,8 @@ DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
 _STATUS = {1: "TK_ERR_ARG", 2: "TK_ERR_RANGE", 3: "TK_ERR_OOM", 4: "TK_ERR_HIP", 5: "TK_ERR_UNSUPPORTED"}
 
 EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "svd_update",
-           "tucker_svd_info", "tucker_qrp_gaps", "core_fit", "core_fit_static",
-           "hooi_sweep", "hooi_run", "reconstruct", "ttmc_adjoint", "tucker_profile", "tucker_profile_read", "tucker_free",
+           "tucker_svd_info", "tucker_qrp_gaps", "tucker_ttmc_kernel", "core_fit", "core_fit_static",
+           "hosvd_init", "hooi_sweep", "hooi_run", "reconstruct", "ttmc_adjoint", "tucker_profile", "tucker_profile_read", "tucker_free",
            "tucker_last_error")
 
 
@@ -55,9 +55,11 @@ def load_library(path: str = LIB_PATH):
     lib.svd_update.argtypes = [P, I, P, P, P]
     lib.tucker_svd_info.argtypes = [P, P]
     lib.tucker_qrp_gaps.argtypes = [P, I, P]
+    lib.tucker_ttmc_kernel.argtypes = [I, P, P, I, I, P]
     lib.core_fit.argtypes = [P, P, P, P, P, P]
     lib.core_fit_static.argtypes = [I, I64, ctypes.c_int32, I64, P, P, ctypes.c_double, P, P, P]
     lib.hooi_sweep.argtypes = [P, P, P, P, P, P]
+    lib.hosvd_init.argtypes = [P, P, P, I, P]
     lib.hooi_run.argtypes = [P, P, P, I, ctypes.c_double, P, P, P]
     lib.reconstruct.argtypes = [P, P, P, I64, P, P, P]
     lib.ttmc_adjoint.argtypes = [P, I, P, P, P, P, P, P]
@@ -229,6 +231,20 @@ def svd_info(ctx: Ctx) -> int:
     return v.value
 
 
+TTMC_KERNELS = {0: "generic", 1: "order3", 2: "fiber"}
+
+
+def ttmc_kernel(dims, ranks, dtype: str, mode: int) -> str:
+    """Which TTMc kernel runs for `mode` of a tensor of this shape ("generic", "order3" or
+    "fiber"); host-only."""
+    N = len(dims)
+    d = (ctypes.c_int64 * N)(*[int(x) for x in dims])
+    r = (ctypes.c_int32 * N)(*[int(x) for x in ranks])
+    k = ctypes.c_int()
+    _check(load_library().tucker_ttmc_kernel(N, d, r, DTYPES[dtype], int(mode), ctypes.byref(k)))
+    return TTMC_KERNELS[k.value]
+
+
 def qrp_gaps(ctx: Ctx, mode: int):
     """Relative pivot gaps of the mode's last QRP (list of R_mode floats; NaN: not recorded)."""
     _mode_ok(ctx, mode)
@@ -271,6 +287,18 @@ def core_fit_static(Y_last: torch.Tensor, U_last: torch.Tensor, normx2: float, G
                                           _dev(G, torch.float64, "G", numel=R * K), _dev(fit, torch.float64, "fit", numel=1),
                                           _stream()))
     return G, fit
+
+
+def hosvd_init(ctx: Ctx, Omega, svd: bool = False, U_out=None):
+    """HOSVD-style initial factors from a Kronecker-structured random sketch of every unfolding:
+    Omega[k] (float64 I_k x R_k, the caller's random test factors) -> U_out[k] (QRP of the
+    sketch, or its leading left singular vectors with svd=True)."""
+    if U_out is None:
+        U_out = [torch.empty((ctx.dims[k], ctx.ranks[k]), dtype=torch.float64, device="cuda")
+                 for k in range(ctx.order)]
+    _check(load_library().hosvd_init(ctx.handle, _ptrs(Omega, ctx, name="Omega"), _ptrs(U_out, ctx, name="U_out"),
+                                     int(bool(svd)), _stream()))
+    return U_out
 
 
 def hooi_sweep(ctx: Ctx, U, G: torch.Tensor | None = None, fit: torch.Tensor | None = None,

@@ -144,10 +144,8 @@ int tucker_init(tk_ctx** out, int order, const int64_t* dims, const int32_t* ran
     int64_t maxn = 0;
     // factor copies: 16 columns (a multiple of 16 above 16), except order >= 4 with every rank
     // <= 8, whose fiber-factored TTMc gathers 8-column rows (half the bytes and cache footprint)
-    bool narrow = order >= 4;
-    for (int t = 0; t < order; ++t) narrow = narrow && ranks[t] <= 8;
     for (int t = 0; t < order; ++t) {
-        c->ldU[t] = narrow ? 8 : pad_rank(ranks[t]);
+        c->ldU[t] = factor_ld(order, ranks, t);
         if ((st = dmalloc(&c->Ulp[t], (size_t)dims[t] * c->ldU[t] * dtype_size(dtype)))) { free_ctx(c); return st; }
         if ((st = fill_zero(c->Ulp[t], (size_t)dims[t] * c->ldU[t] * dtype_size(dtype), s))) { free_ctx(c); return st; }
         const ModeLayout& ml = c->mode[t];
@@ -248,6 +246,17 @@ int svd_update(tk_ctx* ctx, int mode, const void* Y, double* U_out, void* stream
     return st;
 }
 
+int tucker_ttmc_kernel(int order, const int64_t* dims, const int32_t* ranks, int dtype, int mode, int* kernel) {
+    if (order < 2 || order > kMaxOrder) return set_error(TK_ERR_ARG, "order %d outside [2, %d]", order, kMaxOrder);
+    if (!dims || !ranks || !kernel) return set_error(TK_ERR_ARG, "dims/ranks/kernel is null");
+    if (dtype != TK_F64 && dtype != TK_F32 && dtype != TK_BF16) return set_error(TK_ERR_ARG, "unknown dtype %d", dtype);
+    if (mode < 0 || mode >= order) return set_error(TK_ERR_ARG, "mode %d outside [0, %d)", mode, order);
+    for (int t = 0; t < order; ++t)
+        if (dims[t] < 1 || ranks[t] < 1) return set_error(TK_ERR_ARG, "dims and ranks must be positive");
+    *kernel = ttmc_kernel_for(order, dims, ranks, dtype, mode);
+    return TK_OK;
+}
+
 int tucker_qrp_gaps(tk_ctx* ctx, int mode, double* gaps) {
     int st = check_ctx(ctx);
     if (st) return st;
@@ -295,6 +304,30 @@ int core_fit_static(int ytype, int64_t I, int32_t R, int64_t K, const void* Y_la
     int st = pending_error();
     if (st) return st;
     return core_static_run(ytype, I, R, K, Y_last, U_last, normx2, G, fit, (hipStream_t)stream);
+}
+
+int hosvd_init(tk_ctx* ctx, const double* const* Omega, double* const* U_out, int use_svd, void* stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!Omega || !U_out) return set_error(TK_ERR_ARG, "Omega/U_out is null");
+    for (int t = 0; t < ctx->N; ++t) {
+        if (!Omega[t]) return set_error(TK_ERR_ARG, "Omega[%d] is null", t);
+        if (!U_out[t]) return set_error(TK_ERR_ARG, "U_out[%d] is null", t);
+        for (int k = 0; k < ctx->N; ++k)
+            if ((const double*)U_out[t] == Omega[k]) return set_error(TK_ERR_ARG, "U_out[%d] aliases Omega[%d]", t, k);
+    }
+    if ((st = pending_error())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // every mode sketches with the caller's test factors only (not with the modes already done)
+    for (int n = 0; n < ctx->N; ++n) {
+        for (int t = 0; t < ctx->N; ++t)
+            if (t != n && (st = convert_factor(ctx, t, Omega[t], s))) return st;
+        if ((st = ttmc_run(ctx, n, ctx->ws.y, s))) return st;
+        st = use_svd ? svd_run(ctx, n, ctx->ws.y, U_out[n], s) : qrp_run(ctx, n, ctx->ws.y, U_out[n], nullptr, s);
+        if (st) return st;
+    }
+    ctx->last_stream = s;
+    return TK_OK;
 }
 
 int hooi_sweep(tk_ctx* ctx, double* const* U, double* G, double* fit_dev, double* fit_host, void* stream) {

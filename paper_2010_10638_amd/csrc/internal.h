@@ -199,6 +199,10 @@ int fill_f64(double* p, int64_t n, double v, hipStream_t s);   // a kernel, not 
 // val (optional): values on the mode's padded stream to use instead of the tensor's (same type)
 int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main = nullptr,
              const void* val = nullptr);
+// columns of the factor copy of mode t (16, a multiple of 16 above, or 8 for order >= 4 with
+// every rank <= 8) and the TTMc kernel a mode runs (enum tk_ttmc_kernel); host-only
+int factor_ld(int N, const int32_t* ranks, int t);
+int ttmc_kernel_for(int N, const int64_t* dims, const int32_t* ranks, int dtype, int mode);
 // Completion (completion.hip): loss and gradients over the context's entries, parameters in the
 // context's TTMc type (FP32 or FP64)
 int adjoint_run(tk_ctx* ctx, const void* G, const void* const* U, void* loss, void* gG, void* const* gU,

@@ -774,6 +774,48 @@ int launch_fiber(int dtype, const TtmcArgs& a, const FiberArgs& f, int ldc, hipS
 
 }  // namespace
 
+int factor_ld(int N, const int32_t* ranks, int t) {
+    bool narrow = N >= 4;
+    for (int k = 0; k < N; ++k) narrow = narrow && ranks[k] <= 8;
+    return narrow ? 8 : pad_rank(ranks[t]);
+}
+
+int ttmc_kernel_for(int N, const int64_t* dims, const int32_t* ranks, int dtype, int mode) {
+    int others[kMaxOrder - 1], no = 0;
+    for (int t = 0; t < N; ++t)
+        if (t != mode) others[no++] = t;
+    if (N == 3) {
+        bool ok = true;
+        for (int j = 0; j < 2; ++j) {
+            const int t = others[j];
+            const int ld = factor_ld(N, ranks, t);
+            // the order-3 kernels form gather offsets in 32 bits (byte offsets in k_ttmc3_lds,
+            // element offsets in int in k_ttmc3_mfma): only factors below 2^31 bytes take them
+            const bool off32 = (uint64_t)dims[t] * (uint64_t)ld * dtype_size(dtype) < (1ull << 31);
+            ok = ok && ranks[t] <= 16 && ld == 16 && off32;
+        }
+        return ok ? TK_TTMC_ORDER3 : TK_TTMC_GENERIC;
+    }
+    if (N == 4 || N == 5) {
+        // fiber mode = the last other mode; inner modes the others
+        int off = 0, Ks = 1;
+        bool ok = true;
+        for (int k = 0; k < N - 2; ++k) {
+            ok = ok && ranks[others[k]] <= 16;
+            off += ranks[others[k]];
+            Ks *= ranks[others[k]];
+        }
+        for (int j = 0; j < N - 1; ++j) {
+            const int ld = factor_ld(N, ranks, others[j]);
+            ok = ok && (ld == 8 || ld == 16);
+        }
+        const int Rf = ranks[others[N - 2]];
+        ok = ok && off <= kFiberTile && ((Rf <= 8 && Ks <= 64 * 8) || (Rf <= 16 && Ks <= 64 * 4));
+        return ok ? TK_TTMC_FIBER : TK_TTMC_GENERIC;
+    }
+    return TK_TTMC_GENERIC;
+}
+
 int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main, const void* val) {
     const ModeLayout& ml = ctx->mode[mode];
     const int N = ctx->N;
@@ -801,22 +843,19 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
     a.K = (int32_t)ml.K;
     a.Y = Y;
     a.carry = ctx->ws.carry;
-    bool mfma_ok = (N == 3);
     for (int j = 0; j < N - 1; ++j) {
         int t = ml.others[j];
         a.F[j] = ctx->Ulp[t];
         a.ld[j] = ctx->ldU[t];
         a.R[j] = ctx->ranks[t];
-        // the order-3 kernels form gather offsets in 32 bits (byte offsets in k_ttmc3_lds,
-        // element offsets in int in k_ttmc3_mfma): only factors below 2^31 bytes take them
-        const bool off32 = (uint64_t)ctx->dims[t] * (uint64_t)a.ld[j] * dtype_size(ctx->dtype) < (1ull << 31);
-        mfma_ok = mfma_ok && a.R[j] <= 16 && a.ld[j] == 16 && off32;
     }
+    const int kernel = ttmc_kernel_for(N, ctx->dims, ctx->ranks, ctx->dtype, mode);
+    const bool mfma_ok = kernel == TK_TTMC_ORDER3;
     const unsigned grid = (unsigned)((ml.nchunks + 3) / 4);
     int st = TK_OK;
     // fiber-factored kernel for order >= 4 (fiber mode = last other mode)
     FiberArgs fa{};
-    bool fiber_ok = N >= 4 && ml.fiber_slot == N - 2;
+    bool fiber_ok = kernel == TK_TTMC_FIBER && ml.fiber_slot == N - 2;
     if (fiber_ok) {
         fa.nin = N - 2;
         int off = 0;
@@ -831,10 +870,7 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
         }
         fa.Rf = a.R[N - 2];
         fa.tw = off;
-        bool ld_ok = true;
-        for (int j = 0; j < N - 1; ++j) ld_ok = ld_ok && (a.ld[j] == 8 || a.ld[j] == 16);
-        fiber_ok = small && ld_ok && (N == 4 || N == 5) && off <= kFiberTile &&
-                   ((fa.Rf <= 8 && fa.Ks <= 64 * 8) || (fa.Rf <= 16 && fa.Ks <= 64 * 4));
+        fiber_ok = small;   // always true when ttmc_kernel_for chose this kernel
     }
     if (ev_main) TK_HIP(hipEventRecord(ev_main[0], s));
     if (mfma_ok) {

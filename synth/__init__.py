@@ -200,6 +200,37 @@ def completion(seed: int = 5, dims=(100000, 100000, 1000), nnz: int = 30_000_000
     return Workload(name, dims, [R] * 3, coords, vals, U, dtype=dtype, G_init=G0)
 
 
+def image_like(seed: int = 6, shape=(130, 150), R=(30, 30), sweeps: int = 12, dtype: str = "f64") -> Workload:
+    """Order-2 sparse matrix shaped like a thresholded fundus photograph (the retinal-image case
+    of Sec. IV-C, whose data is not available): a smooth radial background, a few dark blobs and
+    bright vessel-like curves branching from one point, intensities in [0, 1]; pixels below a
+    threshold are dropped (about half remain).  Ranks 30 x 30 (a rank above the other mode's rank
+    would exceed K_n = R_other), Gaussian-QR init, 12 sweeps."""
+    rc, rv, rm, ri = streams(seed)
+    H, W = shape
+    yy, xx = np.meshgrid(np.arange(H) / H, np.arange(W) / W, indexing="ij")
+    img = 0.55 * np.exp(-((yy - 0.5) ** 2 + (xx - 0.5) ** 2) / 0.18)
+    for _ in range(5):                                   # darker spots
+        cy, cx, r = rm.random(), rm.random(), 0.02 + 0.05 * rm.random()
+        img -= 0.2 * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * r * r))
+    oy, ox = 0.45 + 0.1 * rm.random(), 0.35 + 0.1 * rm.random()
+    for _ in range(9):                                   # vessels: bent curves from the disc
+        ang = rm.uniform(0, 2 * np.pi)
+        bend = rm.uniform(-1.5, 1.5)
+        t = np.linspace(0, 0.7, 400)
+        cy = oy + t * np.sin(ang + bend * t)
+        cx = ox + t * np.cos(ang + bend * t)
+        for py, px in zip(cy, cx):
+            img += 0.004 * np.exp(-((yy - py) ** 2 + (xx - px) ** 2) / (2 * 0.006 ** 2))
+    img = np.clip(img + 0.03 * rv.standard_normal(img.shape), 0.0, 1.0)
+    keep = img > np.quantile(img, 0.5)
+    coords = np.stack(np.nonzero(keep)).astype(np.int32)
+    vals = img[keep].astype(np.float64)
+    U = [gaussian_qr(ri, d, r) for d, r in zip(shape, R)]
+    return Workload("image_%dx%d_r%d_%s" % (H, W, R[0], dtype), list(shape), list(R), coords, vals, U,
+                    sweeps=sweeps, dtype=dtype)
+
+
 # ---------------------------------------------------------------------------------------------
 # Small structured inputs used by the pins.
 # ---------------------------------------------------------------------------------------------

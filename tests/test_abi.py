@@ -90,3 +90,38 @@ def test_product_and_oracle_are_independent():
                     assert not re.search(rf"\b(import|from)\s+{other}\b", text), (f, other)
                     if d == "paper_2010_10638_amd":
                         assert "oracle" not in text.lower(), f
+
+
+def _kernel(lib, dims, ranks, dtype, mode):
+    N = len(dims)
+    d = (ctypes.c_int64 * N)(*dims)
+    r = (ctypes.c_int32 * N)(*ranks)
+    k = ctypes.c_int(-1)
+    assert lib.tucker_ttmc_kernel(N, d, r, dtype, mode, ctypes.byref(k)) == 0
+    return k.value
+
+
+@pytest.mark.parametrize("dtype,limit", [(1, 1 << 25), (2, 1 << 26), (0, 1 << 24)])
+def test_order3_kernel_only_below_32bit_offsets(lib, dtype, limit):
+    """The order-3 matrix-core kernel forms gather offsets in 32 bits: a mode takes it only while
+    every other factor copy (I_t x 16 columns) stays below 2^31 bytes; at the limit the generic
+    kernel (64-bit offsets) runs instead.  Host-only query, no device needed."""
+    GENERIC, ORDER3 = 0, 1
+    assert _kernel(lib, [1000, limit - 1, 500], [8, 8, 8], dtype, 0) == ORDER3
+    assert _kernel(lib, [1000, limit, 500], [8, 8, 8], dtype, 0) == GENERIC
+    assert _kernel(lib, [1000, limit, 500], [8, 8, 8], dtype, 1) == ORDER3    # mode 1 does not gather U_1
+    assert _kernel(lib, [1000, 900, 500], [17, 8, 8], dtype, 1) == GENERIC   # R above 16
+
+
+def test_kernel_choice_by_order(lib):
+    GENERIC, FIBER = 0, 2
+    assert _kernel(lib, [50, 50, 50, 50], [8, 8, 8, 8], 1, 0) == FIBER
+    assert _kernel(lib, [50, 50, 50, 50], [4, 12, 12, 16], 1, 3) == FIBER
+    assert _kernel(lib, [30, 30, 30, 30], [20, 3, 4, 5], 1, 1) == GENERIC     # inner rank above 16
+    assert _kernel(lib, [9] * 6, [2] * 6, 1, 0) == GENERIC
+    assert _kernel(lib, [300, 250], [6, 6], 1, 0) == GENERIC
+    k = ctypes.c_int()
+    d = (ctypes.c_int64 * 3)(5, 5, 5)
+    r = (ctypes.c_int32 * 3)(2, 2, 2)
+    assert lib.tucker_ttmc_kernel(3, d, r, 1, 3, ctypes.byref(k)) == 1        # mode out of range
+    assert lib.tucker_ttmc_kernel(3, d, r, 9, 0, ctypes.byref(k)) == 1        # unknown dtype

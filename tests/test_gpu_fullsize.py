@@ -264,3 +264,31 @@ def test_completion_fullsize(tk):
         scale = keep.sum() / w.nnz    # the oracle divides by the subset size
         got = gU[n][torch.from_numpy(rows).cuda()].double().cpu().numpy()
         assert rel_fro(got, gUo[n][rows] * scale) <= 1e-5, n
+
+
+def test_order3_factor_beyond_32bit_offsets(tk):
+    """A mode whose gathered factor has 2^25 + 16 rows (its FP32 copy, 16 columns, is above 2^31
+    bytes) runs the generic kernel (64-bit offsets); nonzeros at the highest row indices give the
+    oracle's rows of Y_(0).  The other modes keep the matrix-core kernel."""
+    rng = np.random.default_rng(77)
+    big = (1 << 25) + 16
+    dims, ranks = [600, big, 40], [8, 8, 8]
+    assert tk.ttmc_kernel(dims, ranks, "f32", 0) == "generic"
+    assert tk.ttmc_kernel(dims, ranks, "f32", 1) == "order3"
+    nnz = 6000
+    coords = np.stack([rng.integers(0, dims[0], nnz), rng.integers(0, dims[1], nnz),
+                       rng.integers(0, dims[2], nnz)]).astype(np.int32)
+    coords[1, : nnz // 2] = big - 1 - rng.integers(0, 64, nnz // 2)   # the last rows of U_1
+    coords, vals = oracle.coalesce(coords, rng.standard_normal(nnz), dims)
+    coords = np.ascontiguousarray(coords)
+    U = [rng.standard_normal((d, r)) for d, r in zip(dims, ranks)]
+    c = torch.from_numpy(coords).cuda()
+    v = torch.from_numpy(vals).cuda()
+    ctx = tk.tucker_init(c, v, dims, ranks, dtype="f32")
+    Ud = [torch.from_numpy(u).cuda() for u in U]
+    Y = tk.ttmc_mode(ctx, 0, Ud).double().cpu().numpy()
+    Yo = oracle.ttmc(coords, vals, dims, ranks, 0, U)
+    assert rel_fro(Y, Yo) <= 1e-5
+    Yc = oracle.ttmc(coords, cast_vals(vals, "f32"), dims, ranks, 0, cast_inputs(U, "f32"))
+    for i in np.unique(coords[0]):
+        assert rel_fro(Y[i], Yc[i]) <= 2e-6, i

@@ -389,6 +389,51 @@ def test_qrp_pivot_gaps(tk, K, R):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("svd", [False, True])
+def test_hosvd_init_parity(tk, dtype, svd):
+    """hosvd_init (sketch of every unfolding with the caller's Gaussian test factors, then QRP or
+    SVD) against the oracle's hosvd_sketch on the same test factors: QRP factors to 1e-10 (FP64) /
+    subspaces to 1e-5 (FP32 TTMc); SVD subspaces to 1e-9 (FP64) / 1e-5 (FP32); orthonormal
+    columns.  Test factors are inputs: the library draws no random numbers."""
+    dims, ranks = [300, 250, 200], [8, 6, 5]
+    coords, vals, _, _ = synth.support_low_rank(41, dims, [60, 50, 40], ranks)
+    vals = vals + 1e-3 * np.random.default_rng(43).standard_normal(vals.size) * np.abs(vals).mean()
+    rng = np.random.default_rng(42)
+    Omega = [rng.standard_normal((d, r)) for d, r in zip(dims, ranks)]
+    ctx = tk.tucker_init(*to_dev(coords, vals), dims, ranks, dtype=dtype)
+    Od = dev_list(Omega)
+    U = [u.cpu().numpy() for u in tk.hosvd_init(ctx, Od, svd=svd)]
+    Uo = oracle.hosvd_sketch(coords, vals, dims, ranks, Omega, svd=svd)
+    for n in range(3):
+        np.testing.assert_allclose(U[n].T @ U[n], np.eye(ranks[n]), atol=1e-12)
+        sub = np.linalg.norm(U[n] @ U[n].T - Uo[n] @ Uo[n].T)
+        if dtype == "f64" and not svd:
+            np.testing.assert_allclose(U[n], Uo[n], atol=1e-10)
+        else:
+            assert sub <= (1e-9 if dtype == "f64" else 1e-5), (n, sub)
+    # the test factors are left as they were
+    for n in range(3):
+        assert np.array_equal(Omega[n], Od[n].cpu().numpy())
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_hooi_order2_image(tk, dtype, tol):
+    """Order 2 (no Kronecker product: the TTMc is a sparse-times-dense product), the image-shaped
+    130 x 150 matrix of the retinal case, ranks 30 x 30, 12 sweeps: every fit within the tolerance
+    of the oracle's, the final factors spanning the oracle's subspaces."""
+    w = synth.image_like()
+    Uo, Go, fo, _ = oracle.hooi(w.coords, w.vals, w.dims, w.ranks, w.U_init, w.sweeps)
+    ctx = make(tk, w, dtype)
+    U = dev_list(w.U_init)
+    fits = [tk.hooi_sweep(ctx, U, sync_fit=True)[1] for _ in range(w.sweeps)]
+    np.testing.assert_allclose(fits, fo, rtol=tol, atol=0)
+    assert all(b >= a - 1e-12 for a, b in zip(fits, fits[1:]))   # monotone on this input
+    for n in range(2):
+        Un = U[n].cpu().numpy()
+        assert np.linalg.norm(Un @ Un.T - Uo[n] @ Uo[n].T) <= (1e-9 if dtype == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_core_fit_parity(tk, dtype):
     dims, ranks = [300, 200, 150], [8, 6, 5]
     w = synth.small_uniform(300, dims, ranks, 8000)

@@ -246,6 +246,25 @@ def test_core_identity_any_size():
     assert abs(w.vals @ xh - np.sum(G * G)) < 1e-10 * np.sum(G * G)
 
 
+@pytest.mark.parametrize("svd", [False, True])
+def test_hosvd_sketch_recovers_exact_low_rank_spaces(svd):
+    """On a tensor of exact multilinear rank (sparse support), the sketched HOSVD start (TTMc with
+    Gaussian test factors, then QRP or SVD of each sketch) spans exactly the column space of each
+    factor (projectors equal to round-off), and one HOOI sweep from it reconstructs X to round-off."""
+    dims, support, ranks = [40, 35, 30], [12, 10, 9], [4, 5, 3]
+    coords, vals, G, F = synth.support_low_rank(5, dims, support, ranks)
+    rng = np.random.default_rng(6)
+    Omega = [rng.standard_normal((d, r)) for d, r in zip(dims, ranks)]
+    U = oracle.hosvd_sketch(coords, vals, dims, ranks, Omega, svd=svd)
+    for n in range(3):
+        Qf, _ = np.linalg.qr(F[n])
+        assert np.linalg.norm(U[n] @ U[n].T - Qf @ Qf.T) <= 1e-12 * 10
+        assert np.linalg.norm(U[n].T @ U[n] - np.eye(ranks[n])) <= 1e-12
+    Uh, Gh, fits, _ = oracle.hooi(coords, vals, dims, ranks, U, 1)
+    xhat = oracle.reconstruct(Gh, Uh, coords)
+    assert np.linalg.norm(xhat - vals) <= 1e-12 * np.linalg.norm(vals)
+
+
 def test_first_factor_init_is_unused():
     """Mode 1 of the first sweep reads only U_2..U_N (Alg. 2), so U_1's init cannot matter."""
     w = random_tensor(41, [10, 9, 8], 150, [3, 3, 3])

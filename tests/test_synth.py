@@ -80,3 +80,12 @@ def test_streams_are_independent_of_sizes():
     b = synth.small_uniform(9, [50, 40, 30], [3, 3, 3], 900)
     for u, v in zip(a.U_init, b.U_init):
         np.testing.assert_array_equal(u, v)
+
+
+def test_image_like_shape_and_determinism():
+    a, b = synth.image_like(), synth.image_like()
+    assert a.dims == [130, 150] and a.ranks == [30, 30] and a.sweeps == 12
+    assert np.array_equal(a.coords, b.coords) and np.array_equal(a.vals, b.vals)
+    assert 0.45 <= a.nnz / (130 * 150) <= 0.55
+    assert a.vals.min() > 0.0 and a.vals.max() <= 1.0
+    assert np.unique(a.coords[0] * 150 + a.coords[1]).size == a.nnz
