@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <vector>
 
+#include <cmath>
+
 #include "internal.h"
 
 namespace tk {
@@ -214,6 +216,11 @@ int launch_gather(const int32_t* perm, int64_t D, const int32_t* rowsrc, const G
 // (writes Y_(n) directly); every later piece holding part of that row is a carrier whose partial
 // row sum goes to a carry slot, added to the row by the fix-up pass in slot order.  Equal pieces
 // give every wave the same work whatever the row-length distribution (skewed fibers included).
+#ifndef TK_ROW_WEIGHT
+#define TK_ROW_WEIGHT 32
+#endif
+constexpr int64_t kRowWeight = TK_ROW_WEIGHT;
+
 void make_chunks(const std::vector<int32_t>& ptr, int64_t C, std::vector<int32_t>& cptr,
                  std::vector<int32_t>& crow, std::vector<int32_t>& cslot,
                  std::vector<int32_t>& split, int64_t& ncarry, int32_t& maxrow) {
@@ -228,11 +235,24 @@ void make_chunks(const std::vector<int32_t>& ptr, int64_t C, std::vector<int32_t
     }
     const int64_t quads = D / 4;
     C = std::max<int64_t>(1, std::min<int64_t>(C, quads));
+    // pieces of equal work: an entry weighs 1, a row start kRowWeight more (writing a finished row
+    // and starting the next costs about that many entries' time), so that pieces full of short
+    // rows are not the last to finish
+    const double W = (double)D + (double)kRowWeight * (double)S;
     int64_t r = 0;            // row holding the current piece start
     int64_t open_row = -1;    // row with carry slots being collected
     for (int64_t k = 0; k < C; ++k) {
-        const int64_t q = quads * k / C * 4;
-        if (!cptr.empty() && q == cptr.back()) continue;
+        // first quad boundary q (in row r) with q + kRowWeight * (r + 1) >= W k / C
+        const double target = W * (double)k / (double)C;
+        int64_t q = 0;
+        if (k > 0) {
+            while (r < S - 1 && (double)ptr[r + 1] + (double)kRowWeight * (double)(r + 2) <= target) ++r;
+            const double qa = target - (double)kRowWeight * (double)(r + 1);
+            q = std::max<int64_t>(ptr[r], ((int64_t)std::ceil(qa) + 3) / 4 * 4);
+            if (q >= ptr[r + 1]) q = ptr[r + 1];
+            if (q >= D) break;
+        }
+        if (!cptr.empty() && q <= cptr.back()) continue;
         while (ptr[r + 1] <= q) ++r;
         cptr.push_back((int32_t)q);
         crow.push_back((int32_t)r);
@@ -370,12 +390,13 @@ int build_layout(tk_ctx* ctx, const int32_t* coords, const double* vals, int64_t
 
     // 3. per mode: sort by the mode key, gather the SoA layout, row pointers, chunk table
     const int32_t* dc = (const int32_t*)dco.p;
-    // chunk count: kChunkWavesPerCU resident waves per compute unit, pieces of at least 256 entries
+    // chunk count: kChunkWavesPerCU resident waves per compute unit, pieces of at least 64 entries
+    // (small tensors still spread over many waves; the walk is latency-bound there)
     int ncu = 0;
     TK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
     ctx->ncu = ncu;
     const int64_t nchunk_target =
-        std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(ncu, 1) * kChunkWavesPerCU, D / 256));
+        std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(ncu, 1) * kChunkWavesPerCU, D / 64));
     for (int m = 0; m < N; ++m) {
         ModeLayout& ml = ctx->mode[m];
         int no = 0;

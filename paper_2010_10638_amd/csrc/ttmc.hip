@@ -439,6 +439,8 @@ __global__ __launch_bounds__(256) void k_ttmc_generic(TtmcArgs a) {
         AT acc[KPL];
 #pragma unroll
         for (int j = 0; j < KPL; ++j) acc[j] = AT(0);
+        // unrolled so that the loads of several nonzeros are in flight together
+#pragma unroll 4
         for (int p = q; p < end; ++p) {
             const AT x = load_as<AT, ST>(a.val, p);
             int64_t base[kMaxOrder - 1];
