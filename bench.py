@@ -293,7 +293,39 @@ def run_completion(args, w, tk, torch):
            "config": {"workload": w.name, "dims": w.dims, "ranks": w.ranks, "nnz": nnz, "optimizer": "adam",
                       "parallelism": "single-gpu"},
            "loss": float(loss.item())}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_completion(w, upd)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_completion(w, upd_per_step, sample=100000):
+    """The FP64 oracle's completion loss and gradients (every core entry per observed entry, one
+    host thread) on the first `sample` observed entries, scaled to all entries, plus one Adam
+    update of the parameters in numpy: the time of one completion step on the host."""
+    import numpy as np
+    import oracle
+    oracle.build()
+    model, avail, _ = host_info()
+    c = np.ascontiguousarray(w.coords[:, :sample])
+    v = np.ascontiguousarray(w.vals[:sample])
+    t0 = time.perf_counter()
+    loss, gG, gU = oracle.completion(w.G_init, w.U_init, c, v, w.dims)
+    t_grad = (time.perf_counter() - t0) * w.nnz / sample
+    params = [w.G_init] + list(w.U_init)
+    grads = [gG] + gU
+    m = [np.zeros_like(x) for x in params]
+    s2 = [np.zeros_like(x) for x in params]
+    t0 = time.perf_counter()
+    for x, g, mm, ss in zip(params, grads, m, s2):
+        mm[...] = 0.9 * mm + 0.1 * g
+        ss[...] = 0.999 * ss + 0.001 * g * g
+        _ = x - 1e-2 * (mm / 0.1) / (np.sqrt(ss / 0.001) + 1e-8)
+    t_adam = time.perf_counter() - t0
+    step_s = t_grad + t_adam
+    return dict(value=upd_per_step / step_s, unit="updates/s", cores=1, kind="oracle",
+                sample=f"FP64 oracle loss and gradients on the first {sample} of {w.nnz} observed entries, "
+                       f"scaled to all of them ({t_grad:.1f} s), plus one numpy Adam update ({t_adam * 1e3:.1f} ms)",
+                cpu_model=model, cpus_visible=avail, step_s=step_s)
 
 
 def _K(ranks, n):
