@@ -87,6 +87,47 @@ __global__ void k_w(const AT* __restrict__ U, const AT* __restrict__ Gn, int64_t
     W[e] = acc;
 }
 
+// Fused form: W[i][16 ra + rb] = sum_r U[i][r] Gn[r][ra * Rb + rb] for ra < Ra, rb < Rb, zero
+// elsewhere (r ascending).  Thread c of a block owns entry c of the 16 x 16 block; a block takes
+// kW16Rows rows.  With R = RT known (RT > 0) the block first copies its rows of U into LDS
+// (coalesced, one wait) and each thread keeps its column of Gn in registers; the products then
+// read U from LDS at one address per wave.  RT = 0 is the plain loop for any R.
+constexpr int kW16Rows = 64;
+
+template <int RT>
+__global__ __launch_bounds__(256) void k_w16(const float* __restrict__ U, const float* __restrict__ Gn, int64_t I,
+                                             int R, int Ra, int Rb, float* __restrict__ W) {
+    const int c = threadIdx.x, ra = c >> 4, rb = c & 15;
+    const bool live = ra < Ra && rb < Rb;
+    const int64_t K = (int64_t)Ra * Rb;
+    const float* g = Gn + (live ? ra * Rb + rb : 0);
+    const int64_t i0 = (int64_t)blockIdx.x * kW16Rows;
+    const int64_t i1 = min(I, i0 + kW16Rows);
+    if constexpr (RT > 0) {
+        __shared__ float us[kW16Rows * RT];
+        const int nflt = (int)(i1 - i0) * RT;
+        for (int e = c; e < nflt; e += 256) us[e] = U[i0 * RT + e];
+        float gr[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) gr[r] = g[(int64_t)r * K];
+        __syncthreads();
+        for (int64_t i = i0; i < i1; ++i) {
+            const float* ur = us + (i - i0) * RT;
+            float t = 0.f;
+#pragma unroll
+            for (int r = 0; r < RT; ++r) t += ur[r] * gr[r];
+            W[i * 256 + c] = live ? t : 0.f;
+        }
+    } else {
+        for (int64_t i = i0; i < i1; ++i) {
+            const float* ur = U + i * R;
+            float acc = 0.f;
+            for (int r = 0; r < R; ++r) acc += ur[r] * g[(int64_t)r * K];
+            W[i * 256 + c] = live ? acc : 0.f;
+        }
+    }
+}
+
 struct ResidArgs {
     const int32_t* rowid;
     const int32_t* rows;
@@ -426,13 +467,15 @@ int ensure_ws(tk_ctx* ctx, hipStream_t s) {
     if (w.ready) return TK_OK;
     const int N = ctx->N;
     const size_t at = ytype_size(ctx->dtype);
+    bool fused = ctx->nnz > 0;
+    for (int n = 0; n < N; ++n) fused = fused && ttmc_residual_form(ctx, n);
     int64_t maxP = 0, maxIK = 0, gn = 0, part = 1024;
     for (int n = 0; n < N; ++n) {
         const ModeLayout& ml = ctx->mode[n];
         maxP = std::max(maxP, ml.P);
-        maxIK = std::max<int64_t>(maxIK, ctx->dims[n] * ml.K);
+        maxIK = std::max<int64_t>(maxIK, ctx->dims[n] * (fused ? 256 : ml.K));
         gn += (int64_t)ctx->ranks[n] * ml.K;
-        part = std::max<int64_t>(part, (ml.P + 255) / 256);
+        part = std::max<int64_t>(part, fused ? ml.nchunks : (ml.P + 255) / 256);
         int ns;
         int64_t sl;
         gg_plan(ctx->dims[n], ml.K, ctx->ranks[n], ns, sl);
@@ -448,10 +491,15 @@ int ensure_ws(tk_ctx* ctx, hipStream_t s) {
         return TK_OK;
     };
     int st;
-    if ((st = alloc(&w.e, (size_t)maxP * at)) || (st = alloc(&w.e2, (size_t)maxP * at)) ||
-        (st = alloc(&w.W, (size_t)maxIK * at)) || (st = alloc(&w.Gn, (size_t)gn * at)) ||
+    if ((st = alloc(&w.W, (size_t)maxIK * at)) || (st = alloc(&w.Gn, (size_t)gn * at)) ||
         (st = alloc((void**)&w.part, (size_t)part * 8)))
         return st;
+    if (fused) {   // the residuals never leave the TTMc kernel: no residual arrays, no position maps
+        w.fused = true;
+        w.ready = true;
+        return TK_OK;
+    }
+    if ((st = alloc(&w.e, (size_t)maxP * at)) || (st = alloc(&w.e2, (size_t)maxP * at))) return st;
     for (int n = 0; n < N; ++n) {
         const ModeLayout& ml = ctx->mode[n];
         if ((st = alloc((void**)&w.rowid[n], (size_t)ml.P * 4))) return st;
@@ -527,6 +575,71 @@ int ensure_ws(tk_ctx* ctx, hipStream_t s) {
     return TK_OK;
 }
 
+// gU_n = scale * TTMc_n(E) G_(n)^T, and for the last mode gG = scale * U_N^T TTMc_N(E)
+template <typename AT>
+int gradients(const AT* Y, const AT* Gn, const AT* Un, int64_t I, int R, int64_t K, double scale, bool last,
+              double* part, AT* gUn, AT* gG, hipStream_t s) {
+    if (std::is_same<AT, float>::value && R <= 16 && K % 16 == 0) {
+        k_gu_mfma<<<cdiv(I, 64), 256, 0, s>>>((const float*)Y, (const float*)Gn, I, R, (int)K, scale, (float*)gUn);
+        TK_LAUNCH_CHECK("k_gu_mfma");
+    } else if (R <= 16 && K % 4 == 0 && (size_t)R * K * sizeof(AT) <= 64 * 1024) {
+        k_gu_rows<AT><<<cdiv(I, 256), 256, (size_t)R * K * sizeof(AT), s>>>(Y, Gn, I, R, (int)K, scale, gUn);
+        TK_LAUNCH_CHECK("k_gu_rows");
+    } else {
+        k_gu<AT><<<cdiv(I * R, 256), 256, 0, s>>>(Y, Gn, I, R, K, scale, gUn);
+        TK_LAUNCH_CHECK("k_gu");
+    }
+    if (last) {
+        int nsplit;
+        int64_t slab;
+        gg_plan(I, K, R, nsplit, slab);
+        dim3 grid(cdiv(K, 64), (unsigned)nsplit, cdiv(R, 64));
+        k_gg_partial<AT><<<grid, 256, 0, s>>>(Y, Un, I, (int)K, R, slab, part);
+        TK_LAUNCH_CHECK("k_gg_partial");
+        k_gg_reduce<AT><<<cdiv(K * R, 256), 256, 0, s>>>(part, nsplit, (int)K, R, scale, gG);
+        TK_LAUNCH_CHECK("k_gg_reduce");
+    }
+    return TK_OK;
+}
+
+// Order 3, FP32: per mode, W_n = U_n G_(n) in 16 x 16 blocks and the TTMc over the residuals
+// computed inside the kernel (mode 0's pass also yields the per-chunk loss partials)
+int adjoint_fused(tk_ctx* ctx, const float* G, const float* const* U, float* loss, float* gG, float* const* gU,
+                  double scale, int64_t size, hipStream_t s) {
+    CompletionWs& w = ctx->cws;
+    const int N = ctx->N;
+    float* Gn = (float*)w.Gn;
+    int st;
+    for (int n = 0; n < N; ++n) {
+        const ModeLayout& ml = ctx->mode[n];
+        const int64_t I = ctx->dims[n];
+        const int R = ctx->ranks[n];
+        Unfold u{};
+        for (int t = 0; t < N; ++t) u.R[t] = ctx->ranks[t];
+        u.N = N;
+        u.n = n;
+        u.K = ml.K;
+        u.size = size;
+        k_unfold<float><<<cdiv(size, 256), 256, 0, s>>>(u, G, Gn);
+        TK_LAUNCH_CHECK("k_unfold");
+        const int Ra = ctx->ranks[ml.others[0]], Rb = ctx->ranks[ml.others[1]];
+        const unsigned wgrid = cdiv(I, kW16Rows);
+        if (R == 16) k_w16<16><<<wgrid, 256, 0, s>>>(U[n], Gn, I, R, Ra, Rb, (float*)w.W);
+        else k_w16<0><<<wgrid, 256, 0, s>>>(U[n], Gn, I, R, Ra, Rb, (float*)w.W);
+        TK_LAUNCH_CHECK("k_w16");
+        if ((st = ttmc_residual_run(ctx, n, ctx->ws.y, (const float*)w.W, n == 0 ? w.part : nullptr, s))) return st;
+        if (n == 0) {
+            // the loss partials are consumed before the last mode reuses the buffer
+            k_loss<float><<<1, 1024, 0, s>>>(w.part, ml.nchunks, 0.5 * scale, loss);
+            TK_LAUNCH_CHECK("k_loss");
+        }
+        if ((st = gradients<float>((const float*)ctx->ws.y, Gn, U[n], I, R, ml.K, scale, n == N - 1, w.part, gU[n],
+                                   gG, s)))
+            return st;
+    }
+    return TK_OK;
+}
+
 template <typename AT>
 int adjoint_typed(tk_ctx* ctx, const AT* G, const AT* const* U, AT* loss, AT* gG, AT* const* gU, hipStream_t s) {
     const int N = ctx->N;
@@ -556,6 +669,9 @@ int adjoint_typed(tk_ctx* ctx, const AT* G, const AT* const* U, AT* loss, AT* gG
     int64_t size = 1;
     for (int t = 0; t < N; ++t) size *= ctx->ranks[t];
     AT* Gn = (AT*)w.Gn;
+    if constexpr (std::is_same<AT, float>::value) {
+        if (w.fused) return adjoint_fused(ctx, G, U, loss, gG, gU, scale, size, s);
+    }
     int64_t nblk0 = 0;
     for (int n = 0; n < N; ++n) {
         const ModeLayout& ml = ctx->mode[n];
@@ -611,33 +727,13 @@ int adjoint_typed(tk_ctx* ctx, const AT* G, const AT* const* U, AT* loss, AT* gG
         }
         // TTMc_n(E): the forward kernels with the residuals in place of the values
         if ((st = ttmc_run(ctx, n, ctx->ws.y, s, nullptr, n == 0 ? w.e : w.e2))) return st;
-        const AT* Y = (const AT*)ctx->ws.y;
-        if (std::is_same<AT, float>::value && R <= 16 && K % 16 == 0) {
-            k_gu_mfma<<<cdiv(I, 64), 256, 0, s>>>((const float*)Y, (const float*)Gn, I, R, (int)K, scale,
-                                                  (float*)gU[n]);
-            TK_LAUNCH_CHECK("k_gu_mfma");
-        } else if (R <= 16 && K % 4 == 0 && (size_t)R * K * sizeof(AT) <= 64 * 1024) {
-            k_gu_rows<AT><<<cdiv(I, 256), 256, (size_t)R * K * sizeof(AT), s>>>(Y, Gn, I, R, (int)K, scale, gU[n]);
-            TK_LAUNCH_CHECK("k_gu_rows");
-        } else {
-            k_gu<AT><<<cdiv(I * R, 256), 256, 0, s>>>(Y, Gn, I, R, K, scale, gU[n]);
-            TK_LAUNCH_CHECK("k_gu");
-        }
-        if (n == N - 1) {
-            int nsplit;
-            int64_t slab;
-            gg_plan(I, K, R, nsplit, slab);
-            dim3 grid(cdiv(K, 64), (unsigned)nsplit, cdiv(R, 64));
-            k_gg_partial<AT><<<grid, 256, 0, s>>>(Y, U[n], I, (int)K, R, slab, w.part);
-            TK_LAUNCH_CHECK("k_gg_partial");
-            k_gg_reduce<AT><<<cdiv(K * R, 256), 256, 0, s>>>(w.part, nsplit, (int)K, R, scale, gG);
-            TK_LAUNCH_CHECK("k_gg_reduce");
-        }
         if (n == 0) {
             // the loss partials of mode 0 are consumed before the last mode reuses the buffer
             k_loss<AT><<<1, 1024, 0, s>>>(w.part, nblk0, 0.5 * scale, loss);
             TK_LAUNCH_CHECK("k_loss");
         }
+        if ((st = gradients<AT>((const AT*)ctx->ws.y, Gn, U[n], I, R, K, scale, n == N - 1, w.part, gU[n], gG, s)))
+            return st;
     }
     return TK_OK;
 }

@@ -101,11 +101,12 @@ struct Workspace {
 // Completion (adjoint TTMc) workspace, allocated on the first ttmc_adjoint call
 struct CompletionWs {
     bool ready = false;
+    bool fused = false;              // residuals computed inside the TTMc (order 3, FP32): no e, e2, maps
     int32_t* rowid[kMaxOrder] = {};  // per mode: compressed row of every padded position
     void* e = nullptr;               // residuals on mode 0's padded stream (parameter type)
     void* e2 = nullptr;              // the same residuals on mode n's padded stream, n >= 1
     int32_t* map[kMaxOrder] = {};    // n >= 1: mode-0 padded position of every padded position of mode n (-1: pad)
-    void* W = nullptr;               // U_n G_(n), max_n I_n x K_n
+    void* W = nullptr;               // U_n G_(n), max_n I_n x K_n (fused: max_n I_n x 256, 16 x 16 blocks)
     void* Gn = nullptr;              // mode-n unfolding of the core
     double* part = nullptr;          // loss and core-gradient partials
 };
@@ -203,6 +204,12 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main 
 // every rank <= 8) and the TTMc kernel a mode runs (enum tk_ttmc_kernel); host-only
 int factor_ld(int N, const int32_t* ranks, int t);
 int ttmc_kernel_for(int N, const int64_t* dims, const int32_t* ranks, int dtype, int mode);
+// TTMc of mode n over the residuals e = xhat - x of the entries (padding: 0), xhat from W = the
+// mode's rows of U_n G_(n) as zero-padded 16 x 16 blocks ([I_n][256], FP32); part (optional, one
+// per chunk) receives the chunk's sum of e^2.  Order 3, FP32 context, the order-3 MFMA kernel only
+// (ttmc_residual_form).
+bool ttmc_residual_form(const tk_ctx* ctx, int mode);
+int ttmc_residual_run(tk_ctx* ctx, int mode, void* Y, const float* W, double* part, hipStream_t s);
 // Completion (completion.hip): loss and gradients over the context's entries, parameters in the
 // context's TTMc type (FP32 or FP64)
 int adjoint_run(tk_ctx* ctx, const void* G, const void* const* U, void* loss, void* gG, void* const* gU,

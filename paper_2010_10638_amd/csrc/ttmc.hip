@@ -90,6 +90,20 @@ __device__ inline void zero_gaps_ids(const TtmcArgs& a, int s, int prev_id, int 
         for (int64_t e = (int64_t)(id + 1) * K + lane; e < (int64_t)a.In * K; e += 64) Y[e] = AT(0);
 }
 
+// v + (v of lane l ^ D) for D = 16 or 32, through the lane-swap instructions (no LDS): each lane
+// receives both values of its pair, lower lane first, so the two lanes compute the same sum
+template <int D>
+__device__ inline float pair_sum(float v) {
+    const unsigned u = __float_as_uint(v);
+    if constexpr (D == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+}
+
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
@@ -254,8 +268,28 @@ struct LdsTiles {
     int32_t ib[64];
 };
 
-template <typename ST>
-__global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
+// Residual form (the adjoint of the completion loss): the value of each entry is replaced by its
+// residual e = xhat - x, computed from the rows already in the tile.  With M = row i_n of
+// U_n G_(n) as an R_a x R_b matrix, xhat = a^T M b; a tile of 16 entries of one row takes four
+// 16x16x4 MFMAs for M [b_1 .. b_16] (lane l supplies M[l%16][4(l/16)+c] and b_{l%16}[4(l/16)+c]
+// in MFMA c, so one 16-byte LDS read of the B row and one 16-byte load of M serve all four), and
+// lane l then holds rows 4(l/16)..+3 of column l%16: a 4-term dot with the matching part of a
+// and two cross-lane additions give xhat.  A tile that spans several rows repeats the MFMAs per
+// row.  M of the first two rows of the next batch is loaded one batch ahead (other rows, which
+// occur only for rows shorter than a batch, are loaded on demand).  Padding entries repeat the
+// indices of their row's last entry and coordinates are distinct after coalescing, so an entry
+// that opens no row and repeats its predecessor's indices is padding: its residual is 0.
+// s_waitcnt immediate for vmcnt(0) with the other counters left free (expcnt 7, lgkmcnt 15)
+constexpr int kWaitVm0 = 0x0F70;
+
+struct ResArgs {
+    const float* W;      // [I_n][16 x 16]: row i_n of U_n G_(n), entry (r_a, r_b) at 16 r_a + r_b
+    double* part;        // per-chunk sum of squared residuals, or null
+};
+
+template <typename ST, bool RES>
+__global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a, ResArgs res) {
+    static_assert(!RES || sizeof(ST) == 4, "the residual form reads FP32 tiles");
     constexpr int ROWB = 16 * (int)sizeof(ST);   // bytes of one padded factor row
     constexpr int LPR = ROWB / 16;               // lanes per row in a 16-byte gather
     constexpr int RPI = 64 / LPR;                // rows per gather instruction
@@ -284,7 +318,7 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
     int rbase = s0;
     int rowsv = ld_const(a.rows, min(s0 + lane, a.S - 1));
     int prev_id = (s0 > 0) ? ld_const(a.rows, s0 - 1) : -1;
-    auto flush = [&](int row) {
+    auto flush = [&](int row) __attribute__((always_inline)) {
         const bool owner = (row != s0) || (slot < 0);
         const int id = __builtin_amdgcn_readlane(rowsv, row - rbase);
         const uint64_t base = owner ? (uint64_t)(uintptr_t)a.Y : (uint64_t)(uintptr_t)a.carry;
@@ -298,18 +332,51 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
         if (owner && (id != prev_id + 1 || row == a.S - 1)) zero_gaps_ids<float>(a, row, prev_id, id, lane);
         prev_id = id;
     };
-    auto stream_load = [&](int pstart, int& ra, int& rb, float& rx) {
+    auto stream_load = [&](int pstart, int& ra, int& rb, float& rx) __attribute__((always_inline)) {
         const int qq = pstart + lane;
         const bool v = qq < q1;
-        ra = v ? ia[qq] : 0;
-        rb = v ? ib[qq] : 0;
-        rx = v ? load_as<float, ST>(a.val, qq) : 0.f;
+        if constexpr (RES) {
+            // unconditional loads at a clamped position: with no branch around them the compiler
+            // counts them exactly, and later waits leave the gathers in flight
+            const int qc = max(min(qq, q1 - 1), 0);
+            const int ta = ia[qc], tb = ib[qc];
+            const float tx = load_as<float, ST>(a.val, qc);
+            ra = v ? ta : 0;
+            rb = v ? tb : 0;
+            rx = v ? tx : 0.f;
+        } else {
+            ra = v ? ia[qq] : 0;
+            rb = v ? ib[qq] : 0;
+            rx = v ? load_as<float, ST>(a.val, qq) : 0.f;
+        }
     };
-    auto stage = [&](int xb, int ra, int rb, float rx) -> uint64_t {
+    // residual form: indices of the entry before the batch, and the padding mask of a batch
+    int last_a = -1, last_b = -1;
+    if constexpr (RES) {
+        if (q0 > 0) {
+            last_a = ia[q0 - 1] & kIndexMask;
+            last_b = ib[q0 - 1];
+        }
+    }
+    // stage a batch starting at pstart; in the residual form keep = this lane's entry is a real
+    // one (not padding, not past the chunk end), and the values go to the tile only as residuals
+    auto stage = [&](int xb, int ra, int rb, float rx, int pstart, bool& keep) __attribute__((always_inline)) -> uint64_t {
         const uint64_t st = __ballot(ra < 0);
+        if constexpr (RES) {
+            const int ma = ra & kIndexMask;
+            int pa = __shfl(ma, (lane + 63) & 63);
+            int pb = __shfl(rb, (lane + 63) & 63);
+            if (lane == 0) {
+                pa = last_a;
+                pb = last_b;
+            }
+            keep = pstart + lane < q1 && !(ra >= 0 && ma == pa && rb == pb);
+            last_a = __builtin_amdgcn_readlane(ma, 63);
+            last_b = __builtin_amdgcn_readlane(rb, 63);
+        }
         T.ia[lane] = ra & kIndexMask;
         T.ib[lane] = rb;
-        T.x[xb][(lane & 3) * 16 + (lane >> 2)] = rx;
+        if constexpr (!RES) T.x[xb][(lane & 3) * 16 + (lane >> 2)] = rx;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -327,8 +394,8 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
     }
 #define TK_P1(j, va, vb)                                                                            \
     if constexpr (NI > j) {                                                                         \
-        *(uint4*)((char*)T.A + j * 1024 + lane * 16) = va;                                          \
-        *(uint4*)((char*)T.B + j * 1024 + lane * 16) = vb;                                          \
+        *(uint4*)((char*)T.A + j * 1024 + put_off) = va;                                            \
+        *(uint4*)((char*)T.B + j * 1024 + put_off) = vb;                                            \
     }
 #define TK_GATHER()                                                                                 \
     TK_G1(0, ga0, gb0) TK_G1(1, ga1, gb1) TK_G1(2, ga2, gb2) TK_G1(3, ga3, gb3)
@@ -338,18 +405,48 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
     __builtin_amdgcn_wave_barrier();                                                                \
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     uint4 ga0, ga1, ga2, ga3, gb0, gb1, gb2, gb3;
+    // Tile layout.  The residual form reads 16-byte column groups of 16 different entries at a
+    // row stride of 64 bytes, which would fall on the same banks: there the group g of entry n is
+    // stored at group g ^ ((n >> 2) & 3) (a permutation within the row, so the column reads of the
+    // MFMA steps stay conflict-free too: column c of entry e sits at c ^ (4 ((e >> 2) & 3))).
+    // The gather puts lane l's 16 bytes (entry 16 j + l / 4, group l % 4) into the tile.
+    const int put_off = RES ? (lane >> 2) * 64 + 16 * ((lane & 3) ^ ((lane >> 4) & 3)) : lane * 16;
+
+    // residual form: M of rows mr0 and mr1 (16 bytes of each per lane), the wave's sum of e^2
+    float4 Mc0 = make_float4(0.f, 0.f, 0.f, 0.f), Mc1 = Mc0;
+    int mr0 = -1, mr1 = -1;
+    double e2sum = 0.0;
+    const float* const Wlane = res.W + m * 16 + 4 * kq;   // this lane's 16 bytes of a block
+    auto loadM = [Wlane](int id) __attribute__((always_inline)) -> float4 { return *(const float4*)(Wlane + (int64_t)id * 256); };
+    // the first two rows of a batch whose first row index is sfirst and row flags are opens
+    auto fetch_pair = [&](int sfirst, uint64_t opens, int rows_lane) __attribute__((always_inline)) {
+        const int nr0 = sfirst + (int)(opens & 1ull);
+        if (nr0 != mr0) {
+            if (nr0 == mr1) Mc0 = Mc1;
+            else Mc0 = loadM(__builtin_amdgcn_readlane(rows_lane, nr0 - sfirst));
+            mr0 = nr0;
+        }
+        if ((opens & ~1ull) != 0 && mr1 != nr0 + 1) {
+            Mc1 = loadM(__builtin_amdgcn_readlane(rows_lane, nr0 + 1 - sfirst));
+            mr1 = nr0 + 1;
+        }
+    };
 
     // prologue: batch 0 staged and its rows in LDS; stream registers for batches 1 and 2
     int r1a = 0, r1b = 0, r2a = 0, r2b = 0;
     float r1x = 0.f, r2x = 0.f;
     uint64_t starts;
+    bool keep = false;     // residual form: this lane's entry of the current batch is real
+    float xcur = 0.f;      // residual form: its value
     {
         int r0a, r0b;
         float r0x;
         stream_load(q0, r0a, r0b, r0x);
         if (q0 + 64 < q1) stream_load(q0 + 64, r1a, r1b, r1x);
         if (q0 + 128 < q1) stream_load(q0 + 128, r2a, r2b, r2x);
-        starts = stage(0, r0a, r0b, r0x);
+        starts = stage(0, r0a, r0b, r0x, q0, keep);
+        xcur = r0x;
+        if constexpr (RES) fetch_pair(s0, starts & ~1ull, rowsv);
         TK_GATHER()
         TK_PUT()
     }
@@ -359,54 +456,135 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a) {
         const bool plain = starts == 0 || (starts == 1ull && p == q0);   // no row opens inside
         // 1. stage batch b+1 (past the chunk end: zero values at row 0), gather its rows, then the
         //    stream loads of batch b+3; the gathers fly while batch b runs
-        const uint64_t starts_next = stage(xb ^ 1, r1a, r1b, r1x);
+        bool keep_next = false;
+        const float xnext = r1x;
+        const uint64_t starts_next = stage(xb ^ 1, r1a, r1b, r1x, p + 64, keep_next);
         // first row of batch b+1: this batch's row plus the rows opened inside it
         const int s_next = s + __popcll(starts & ~((p == q0) ? 1ull : 0ull));
         const int rows_next = ld_const(a.rows, min(s_next + lane, a.S - 1));
         TK_GATHER()
         r1a = r2a; r1b = r2b; r1x = r2x;
-        if (p + 192 < q1) stream_load(p + 192, r2a, r2b, r2x);
+        if (RES || p + 192 < q1) stream_load(p + 192, r2a, r2b, r2x);
+        if constexpr (RES) {
+            // residuals of batch b into its value slots (padding and entries past the end: 0)
+            const int nvalid = min(64, q1 - p);
+            const uint64_t opens = starts & ~((p == q0) ? 1ull : 0ull);
+            auto upto = [](int n) __attribute__((always_inline)) -> uint64_t { return (n >= 63) ? ~0ull : ((2ull << n) - 1); };
+            // M of row rr: slot 0 or 1; a third row in one batch is loaded into slot 1 and waited
+            // for there, so that the common path keeps the gathers in flight
+#define TK_PICK_M(rr, M)                                                                            \
+    if ((rr) != mr0 && (rr) != mr1) {                                                               \
+        Mc1 = loadM(__builtin_amdgcn_readlane(rowsv, (rr) - s));                                    \
+        mr1 = (rr);                                                                                 \
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);                                                       \
+    }                                                                                               \
+    float4 M = Mc1;                                                                                 \
+    if ((rr) == mr0) M = Mc0;
+            auto tile_model = [](float4 M, float4 bq, float4 aq) __attribute__((always_inline)) -> float {
+                f4_t d = {0, 0, 0, 0};
+                d = Acc<float>::mfma(M.x, bq.x, d);
+                d = Acc<float>::mfma(M.y, bq.y, d);
+                d = Acc<float>::mfma(M.z, bq.z, d);
+                d = Acc<float>::mfma(M.w, bq.w, d);
+                return ((d[0] * aq.x + d[1] * aq.y) + d[2] * aq.z) + d[3] * aq.w;
+            };
+            float mine = 0.f;   // model value of entry `lane` of the batch
+#pragma unroll 1
+            for (int j = 0; j < 4; ++j) {
+                if (16 * j < nvalid) {
+                    const int n = 16 * j + m;
+                    const int col = n * 16 + 4 * (kq ^ ((m >> 2) & 3));   // group kq of entry n
+                    const float4 bq = *(const float4*)((const float*)T.B + col);
+                    const float4 aq = *(const float4*)((const float*)T.A + col);
+                    // rows of the tile: the row of entry 16 j and one more per row opened inside
+                    const int rlo = s + __popcll(opens & upto(16 * j));
+                    const int rhi = rlo + __popcll(opens & (0xFFFEull << (16 * j)));
+                    float xh;
+                    if (rlo == rhi) {
+                        TK_PICK_M(rlo, M0)
+                        xh = tile_model(M0, bq, aq);
+                    } else {
+                        const int rme = s + __popcll(opens & upto(n));
+                        xh = 0.f;
+                        for (int rr = rlo; rr <= rhi; ++rr) {
+                            TK_PICK_M(rr, Mr)
+                            const float part = tile_model(Mr, bq, aq);
+                            if (rr == rme) xh = part;
+                        }
+                    }
+#undef TK_PICK_M
+                    xh = pair_sum<16>(xh);
+                    xh = pair_sum<32>(xh);
+                    if (kq == j) mine = xh;
+                }
+            }
+            const float e = keep ? mine - xcur : 0.f;
+            T.x[xb][(lane & 3) * 16 + (lane >> 2)] = e;
+            e2sum += (double)e * (double)e;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // M of batch b+1's first two rows: issued after the gathers, so the tile writes at
+            // the end of the iteration do not wait for them
+            fetch_pair(s_next, starts_next, rows_next);
+        }
         // 2. batch b's MFMA steps from the LDS tile
-        auto operand = [&](int t, float& av, float& bv) {
-            const int e = (4 * t + kq) * 16 + m;
+        auto operand = [&](int t, float& av, float& bv) __attribute__((always_inline)) {
+            const int e = (4 * t + kq) * 16 + (RES ? (m ^ (4 * (t & 3))) : m);
             if constexpr (sizeof(ST) == 4) { av = T.A[e]; bv = T.B[e]; }
             else { av = bf16_to_f32(T.A[e]); bv = bf16_to_f32(T.B[e]); }
             av *= T.x[xb][kq * 16 + t];
         };
+        // (the residual form, which holds more registers, reads the operands in two halves)
+        constexpr int CH = RES ? 4 : 16;
         if (plain) {
-            float av[16], bv[16];
 #pragma unroll
-            for (int t = 0; t < 16; ++t) operand(t, av[t], bv[t]);
+            for (int t0 = 0; t0 < 16; t0 += CH) {
+                float av[CH], bv[CH];
 #pragma unroll
-            for (int t = 0; t < 16; ++t)
-                if (t < nsteps) acc = Acc<float>::mfma(av[t], bv[t], acc);
+                for (int t = 0; t < CH; ++t) operand(t0 + t, av[t], bv[t]);
+#pragma unroll
+                for (int t = 0; t < CH; ++t)
+                    if (t0 + t < nsteps) acc = Acc<float>::mfma(av[t], bv[t], acc);
+            }
         } else {
-            // rows open inside the batch: every operand is read first, then the unrolled steps
+            // rows open inside the batch: the operands are read first, then the unrolled steps
             // write a finished row out before the step that opens the next one
-            float av[16], bv[16];
-#pragma unroll
-            for (int t = 0; t < 16; ++t) operand(t, av[t], bv[t]);
             const uint64_t opens = starts & ~((p == q0) ? 1ull : 0ull);
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                if (t < nsteps) {
-                    if ((opens >> (4 * t)) & 1ull) {
-                        flush(s);
-                        ++s;
-                        acc = f4_t{0, 0, 0, 0};
+            for (int t0 = 0; t0 < 16; t0 += CH) {
+                float av[CH], bv[CH];
+#pragma unroll
+                for (int t = 0; t < CH; ++t) operand(t0 + t, av[t], bv[t]);
+#pragma unroll
+                for (int t = 0; t < CH; ++t) {
+                    if (t0 + t < nsteps) {
+                        if ((opens >> (4 * (t0 + t))) & 1ull) {
+                            flush(s);
+                            ++s;
+                            acc = f4_t{0, 0, 0, 0};
+                        }
+                        acc = Acc<float>::mfma(av[t], bv[t], acc);
                     }
-                    acc = Acc<float>::mfma(av[t], bv[t], acc);
                 }
             }
         }
         // 4. batch b+1's rows into the tile
         TK_PUT()
         starts = starts_next;
+        keep = keep_next;
+        xcur = xnext;
         xb ^= 1;
         rbase = s_next;
         rowsv = rows_next;
     }
     flush(s);
+    if constexpr (RES) {
+        if (res.part) {
+            for (int o = 32; o > 0; o >>= 1) e2sum += __shfl_xor(e2sum, o);
+            if (lane == 0) res.part[ch] = e2sum;
+        }
+    }
 #undef TK_G1
 #undef TK_P1
 #undef TK_GATHER
@@ -818,17 +996,11 @@ int ttmc_kernel_for(int N, const int64_t* dims, const int32_t* ranks, int dtype,
     return TK_TTMC_GENERIC;
 }
 
-int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main, const void* val) {
+namespace {
+
+TtmcArgs mode_args(tk_ctx* ctx, int mode, void* Y, const void* val) {
     const ModeLayout& ml = ctx->mode[mode];
     const int N = ctx->N;
-    const int64_t In = ctx->dims[mode];
-    const size_t ysz = ytype_size(ctx->dtype);
-    if (ml.nchunks == 0) {
-        if (ev_main) TK_HIP(hipEventRecord(ev_main[0], s));
-        const int st0 = fill_zero(Y, (size_t)In * ml.K * ysz, s);
-        if (ev_main) TK_HIP(hipEventRecord(ev_main[1], s));
-        return st0;
-    }
     TtmcArgs a{};
     a.chunk_ptr = ml.chunk_ptr;
     a.chunk_row = ml.chunk_row;
@@ -837,7 +1009,7 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
     a.ptr = ml.pptr;
     a.rows = ml.rows;
     a.S = (int32_t)ml.S;
-    a.In = (int32_t)In;
+    a.In = (int32_t)ctx->dims[mode];
     a.idx = ml.idx;
     a.nnz = ml.P;
     a.val = val ? val : ml.val;
@@ -851,6 +1023,53 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
         a.ld[j] = ctx->ldU[t];
         a.R[j] = ctx->ranks[t];
     }
+    return a;
+}
+
+int run_fixup(tk_ctx* ctx, const ModeLayout& ml, void* Y, hipStream_t s) {
+    if (ml.nsplit > 0) {
+        if (ctx->dtype == TK_F64)
+            k_ttmc_fixup<double><<<(unsigned)ml.nsplit, 256, 0, s>>>(ml.split, ml.rows, (int)ml.K,
+                                                                     (const double*)ctx->ws.carry, (double*)Y);
+        else
+            k_ttmc_fixup<float><<<(unsigned)ml.nsplit, 256, 0, s>>>(ml.split, ml.rows, (int)ml.K,
+                                                                    (const float*)ctx->ws.carry, (float*)Y);
+        TK_LAUNCH_CHECK("k_ttmc_fixup");
+    }
+    return TK_OK;
+}
+
+}  // namespace
+
+bool ttmc_residual_form(const tk_ctx* ctx, int mode) {
+    return ctx->N == 3 && ctx->dtype == TK_F32 &&
+           ttmc_kernel_for(ctx->N, ctx->dims, ctx->ranks, ctx->dtype, mode) == TK_TTMC_ORDER3;
+}
+
+int ttmc_residual_run(tk_ctx* ctx, int mode, void* Y, const float* W, double* part, hipStream_t s) {
+    const ModeLayout& ml = ctx->mode[mode];
+    if (!ttmc_residual_form(ctx, mode))
+        return set_error(TK_ERR_ARG, "residual TTMc: mode %d does not take the order-3 FP32 kernel", mode);
+    if (ml.nchunks == 0) return fill_zero(Y, (size_t)ctx->dims[mode] * ml.K * sizeof(float), s);
+    const TtmcArgs a = mode_args(ctx, mode, Y, nullptr);
+    ResArgs r{W, part};
+    k_ttmc3_lds<float, true><<<(unsigned)((ml.nchunks + 3) / 4), 256, 0, s>>>(a, r);
+    TK_LAUNCH_CHECK("k_ttmc3_lds");
+    return run_fixup(ctx, ml, Y, s);
+}
+
+int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main, const void* val) {
+    const ModeLayout& ml = ctx->mode[mode];
+    const int N = ctx->N;
+    const int64_t In = ctx->dims[mode];
+    const size_t ysz = ytype_size(ctx->dtype);
+    if (ml.nchunks == 0) {
+        if (ev_main) TK_HIP(hipEventRecord(ev_main[0], s));
+        const int st0 = fill_zero(Y, (size_t)In * ml.K * ysz, s);
+        if (ev_main) TK_HIP(hipEventRecord(ev_main[1], s));
+        return st0;
+    }
+    TtmcArgs a = mode_args(ctx, mode, Y, val);
     const int kernel = ttmc_kernel_for(N, ctx->dims, ctx->ranks, ctx->dtype, mode);
     const bool mfma_ok = kernel == TK_TTMC_ORDER3;
     const unsigned grid = (unsigned)((ml.nchunks + 3) / 4);
@@ -880,10 +1099,10 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
             k_ttmc3_mfma<double, double><<<grid, 256, 0, s>>>(a);
             TK_LAUNCH_CHECK("k_ttmc3_mfma");
         } else if (ctx->dtype == TK_F32) {
-            k_ttmc3_lds<float><<<grid, 256, 0, s>>>(a);
+            k_ttmc3_lds<float, false><<<grid, 256, 0, s>>>(a, ResArgs{});
             TK_LAUNCH_CHECK("k_ttmc3_lds");
         } else {
-            k_ttmc3_lds<bf16_t><<<grid, 256, 0, s>>>(a);
+            k_ttmc3_lds<bf16_t, false><<<grid, 256, 0, s>>>(a, ResArgs{});
             TK_LAUNCH_CHECK("k_ttmc3_lds");
         }
     } else if (fiber_ok) {
@@ -899,16 +1118,7 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
         if (st) return st;
     }
     if (ev_main) TK_HIP(hipEventRecord(ev_main[1], s));
-    if (ml.nsplit > 0) {
-        if (ctx->dtype == TK_F64)
-            k_ttmc_fixup<double><<<(unsigned)ml.nsplit, 256, 0, s>>>(ml.split, ml.rows, (int)ml.K,
-                                                                     (const double*)ctx->ws.carry, (double*)Y);
-        else
-            k_ttmc_fixup<float><<<(unsigned)ml.nsplit, 256, 0, s>>>(ml.split, ml.rows, (int)ml.K,
-                                                                    (const float*)ctx->ws.carry, (float*)Y);
-        TK_LAUNCH_CHECK("k_ttmc_fixup");
-    }
-    return TK_OK;
+    return run_fixup(ctx, ml, Y, s);
 }
 
 }  // namespace tk

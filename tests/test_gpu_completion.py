@@ -76,6 +76,61 @@ def test_adjoint_f32_within_1e5(tk, case):
         assert rel_fro(gU[n], gUo[n]) <= 1e-5, n
 
 
+# FP32 order-3 instances on which every mode takes the matrix-core TTMc, so the residuals are
+# formed inside it: (dims, ranks, nnz, what the layout exercises)
+FUSED_CASES = [
+    ([16, 400, 400], [16, 16, 16], 30000, "rows of ~1,900 entries cut into pieces (carry slots)"),
+    ([20000, 50, 40], [16, 5, 9], 8000, "rows of 1-3 entries: tiles and batches spanning many rows"),
+    ([700, 900, 64], [7, 16, 3], 50000, "unequal ranks below 16 (zero-padded blocks), ragged rows"),
+    ([40, 40, 24], [8, 16, 8], 38400, "every coordinate observed (no padding in any row)"),
+]
+
+
+def fused_instance(case):
+    dims, ranks, nnz, _ = FUSED_CASES[case]
+    rng = np.random.default_rng(850 + case)
+    if nnz == int(np.prod(dims)):
+        coords = np.stack(np.unravel_index(np.arange(nnz), dims)).astype(np.int32)
+    else:
+        coords = np.stack([rng.integers(0, d, nnz) for d in dims]).astype(np.int32)
+    vals = rng.standard_normal(nnz)
+    vals[::7] = 0.0                      # observed zeros are entries like any other
+    coords, vals = oracle.coalesce(coords, vals, dims)
+    w = synth.Workload("fused", dims, ranks, np.ascontiguousarray(coords), vals, None)
+    G = rng.standard_normal(tuple(ranks))
+    U = [rng.standard_normal((d, r)) / np.sqrt(r) for d, r in zip(dims, ranks)]
+    return w, G, U
+
+
+@pytest.mark.parametrize("case", range(len(FUSED_CASES)), ids=[c[3].split(":")[0][:24] for c in FUSED_CASES])
+def test_adjoint_f32_residual_form(tk, case):
+    """The residual-in-TTMc path (order 3, FP32, every mode on the matrix-core kernel) against the
+    oracle on the FP32-rounded inputs: loss and every gradient within 1e-5."""
+    w, G, U = fused_instance(case)
+    for n in range(3):
+        assert tk.ttmc_kernel(w.dims, w.ranks, "f32", n) == "order3"
+    _, loss, gG, gU = run(tk, w, G, U, "f32")
+    r32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    lo, gGo, gUo = oracle.completion(r32(G), [r32(u) for u in U], w.coords, r32(w.vals), w.dims)
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    assert rel_fro(gG, gGo) <= 1e-5
+    for n in range(3):
+        assert rel_fro(gU[n], gUo[n]) <= 1e-5, n
+
+
+def test_adjoint_f32_repeated_calls_agree(tk):
+    """Two calls on one context give bit-identical results (fixed summation order)."""
+    w, G, U = fused_instance(1)
+    ctx, l1, gG1, gU1 = run(tk, w, G, U, "f32")
+    Gd = torch.from_numpy(G).float().cuda()
+    Ud = [torch.from_numpy(u).float().cuda() for u in U]
+    l2, gG2, gU2 = tk.ttmc_adjoint(ctx, Gd, Ud)
+    assert float(l2.item()) == l1
+    assert np.array_equal(gG2.double().cpu().numpy(), gG1)
+    for a, b in zip(gU2, gU1):
+        assert np.array_equal(a.double().cpu().numpy(), b)
+
+
 def test_adjoint_duplicates_and_zero_residual(tk):
     """Duplicates are summed at init (|Omega| counts distinct entries); values equal to the model
     give a zero loss and zero gradients."""
