@@ -341,7 +341,8 @@ def run_sweeps(args, w, tk, torch, profile=True):
     region events for the breakdown).  Returns the measurements and the context."""
     coords = torch.from_numpy(w.coords).cuda()
     vals = torch.from_numpy(w.vals).cuda()
-    ctx = tk.tucker_init(coords, vals, w.dims, w.ranks, dtype=w.dtype, svd=args.factor == "svd")
+    ctx = tk.tucker_init(coords, vals, w.dims, w.ranks, dtype=w.dtype, svd=args.factor == "svd",
+                         memo=not args.no_memo)
     del coords, vals
     info = tk.tucker_get_info(ctx)
     U = [torch.from_numpy(u).cuda() for u in w.U_init]
@@ -435,6 +436,8 @@ def main():
                     "50,000 x 50,000 x 5,000 x 100, 20M nnz, R 8; image: order 2, 130 x 150 image-shaped, R 30, "
                     "FP64; completion: 100,000 x 100,000 x 1,000, "
                     "30M entries, R 16, one Adam step of the completion loss per step")
+    ap.add_argument("--no-memo", action="store_true",
+                    help="order >= 4: form the last two modes' TTMc from the nonzeros (no shared fiber sums)")
     ap.add_argument("--factor", default="qrp", choices=["qrp", "svd"],
                     help="factor update of the HOOI sweeps: qrp (Alg. 2, default) or svd (Alg. 1, the "
                     "leading left singular vectors; not the bench line)")

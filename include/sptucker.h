@@ -61,6 +61,7 @@ enum tk_dtype { TK_F64 = 0, TK_F32 = 1, TK_BF16 = 2 };
 #define TK_FLAG_NO_FAT_RULE 0x1u     /* factor a fat Y_(n) directly instead of Y_(n) Y_(n)^T */
 #define TK_FLAG_SVD         0x2u     /* hooi_sweep updates each factor by svd_update (Alg. 1) */
 #define TK_FLAG_SVD_LIB     0x4u     /* svd_update: rocSOLVER dsyevd for every eigenproblem */
+#define TK_FLAG_NO_MEMO     0x8u     /* hooi_sweep: every mode's TTMc from the nonzeros (no shared sums) */
 
 #define TK_MAX_ORDER 8               /* 2 <= N <= TK_MAX_ORDER */
 #define TK_MAX_KCOLS 4096            /* K_n = prod_{t != n} R_t must not exceed this */
@@ -117,6 +118,28 @@ int tucker_get_csf(tk_ctx* ctx, int mode, int32_t* rows, int64_t* ptr, int32_t* 
  * The factors are converted to the context's TTMc precision on the stream before the product.
  */
 int ttmc_mode(tk_ctx* ctx, int mode, const double* const* U, void* Y, void* stream);
+
+/*
+ * ttmc_memo_pair - the TTMc of the last two modes with shared partial sums (order >= 4).  The
+ * reuse of Sec. III-C (a Kronecker product formed once for the nonzeros sharing its indices)
+ * carried across the modes N-2 and N-1, which follow each other in a sweep (Alg. 2): mode N-2's
+ * fiber kernel forms, for every fiber (i_{N-2}, i_{N-1}), the inner sum
+ * T = sum x kron_{k < N-2} U_k(i_k, :), and mode N-1's TTMc is then a sum over fibers,
+ * Y_(N-1)(i_{N-1}, c R_{N-2} + r) = sum_{i_{N-2}} T(i_{N-2}, i_{N-1}, c) U_{N-2}(i_{N-2}, r).
+ *   U       host array of N device pointers to FP64 factors (I_k x R_k); U[N-2] is not read
+ *   U_next  device FP64 I_{N-2} x R_{N-2}: the U_{N-2} that the second product uses (in a sweep,
+ *           mode N-2's updated factor)
+ *   Y_a     device, I_{N-2} x K_{N-2}: TTMc of mode N-2 with U (as ttmc_mode)
+ *   Y_b     device, I_{N-1} x K_{N-1}: TTMc of mode N-1 with U, U[N-2] replaced by U_next
+ * Both in the context's Y type (double for TK_F64, float otherwise); every entry is written.
+ * hooi_sweep runs modes N-2 and N-1 this way unless the context has TK_FLAG_NO_MEMO or mode
+ * N-2's fibers hold fewer than 4 nonzeros on average.  The first call builds the fiber table
+ * (kept by the context; the fiber sums take pieces x prod_{k<N-2} R_k values of the Y type).
+ * Errors: TK_ERR_UNSUPPORTED below order 4, when mode N-2 does not run the fiber kernel
+ * (tucker_ttmc_kernel), or prod_{k<N-2} R_k > 512 or R_{N-2} > 16; TK_ERR_ARG for null pointers;
+ * TK_ERR_OOM.
+ */
+int ttmc_memo_pair(tk_ctx* ctx, const double* const* U, const double* U_next, void* Y_a, void* Y_b, void* stream);
 
 /*
  * qrp_update - U_n <- QRP(Y_(n), R_n) (Alg. 2; Sec. III-D): the first R_n columns of Q of a QR

@@ -19,10 +19,11 @@ TK_F64, TK_F32, TK_BF16 = 0, 1, 2
 TK_FLAG_NO_FAT_RULE = 0x1
 TK_FLAG_SVD = 0x2
 TK_FLAG_SVD_LIB = 0x4
+TK_FLAG_NO_MEMO = 0x8
 DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
 _STATUS = {1: "TK_ERR_ARG", 2: "TK_ERR_RANGE", 3: "TK_ERR_OOM", 4: "TK_ERR_HIP", 5: "TK_ERR_UNSUPPORTED"}
 
-EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "qrp_update", "svd_update",
+EXPORTS = ("tucker_init", "tucker_get_info", "tucker_get_csf", "ttmc_mode", "ttmc_memo_pair", "qrp_update", "svd_update",
            "tucker_svd_info", "tucker_qrp_gaps", "tucker_ttmc_kernel", "core_fit", "core_fit_static",
            "hosvd_init", "hooi_sweep", "hooi_run", "reconstruct", "ttmc_adjoint", "tucker_profile", "tucker_profile_read", "tucker_free",
            "tucker_last_error")
@@ -51,6 +52,7 @@ def load_library(path: str = LIB_PATH):
     lib.tucker_get_info.argtypes = [P, P, P, P, P]
     lib.tucker_get_csf.argtypes = [P, I, P, P, P, P, P]
     lib.ttmc_mode.argtypes = [P, I, P, P, P]
+    lib.ttmc_memo_pair.argtypes = [P, P, P, P, P, P]
     lib.qrp_update.argtypes = [P, I, P, P, P, P]
     lib.svd_update.argtypes = [P, I, P, P, P]
     lib.tucker_svd_info.argtypes = [P, P]
@@ -144,10 +146,11 @@ class Ctx:
 
 
 def tucker_init(coords: torch.Tensor, vals: torch.Tensor, dims, ranks, dtype: str = "f32",
-                fat_rule: bool = True, svd: bool = False, svd_lib: bool = False) -> Ctx:
+                fat_rule: bool = True, svd: bool = False, svd_lib: bool = False, memo: bool = True) -> Ctx:
     """coords: int32 [N, nnz] (0-based), vals: float64 [nnz], both on the GPU.  svd: hooi_sweep
     updates the factors by svd_update instead of qrp_update.  svd_lib: svd_update uses rocSOLVER's
-    dsyevd for every eigenproblem instead of the library's own subspace iteration."""
+    dsyevd for every eigenproblem instead of the library's own subspace iteration.  memo=False:
+    hooi_sweep forms every mode's TTMc from the nonzeros (no sums shared by the last two modes)."""
     lib = load_library()
     N = len(dims)
     if coords.dim() != 2 or coords.shape[0] != N:
@@ -159,7 +162,7 @@ def tucker_init(coords: torch.Tensor, vals: torch.Tensor, dims, ranks, dtype: st
     r = (ctypes.c_int32 * N)(*[int(x) for x in ranks])
     h = ctypes.c_void_p()
     flags = ((0 if fat_rule else TK_FLAG_NO_FAT_RULE) | (TK_FLAG_SVD if svd else 0)
-             | (TK_FLAG_SVD_LIB if svd_lib else 0))
+             | (TK_FLAG_SVD_LIB if svd_lib else 0) | (0 if memo else TK_FLAG_NO_MEMO))
     cp = _dev(coords, torch.int32, "coords") if nnz else None
     vp = _dev(vals, torch.float64, "vals") if nnz else None
     _check(lib.tucker_init(ctypes.byref(h), N, d, r, nnz, cp, vp, DTYPES[dtype], flags, _stream()))
@@ -198,6 +201,21 @@ def ttmc_mode(ctx: Ctx, mode: int, U, Y: torch.Tensor | None = None) -> torch.Te
     yp = _dev(Y, ctx.ytype, "Y", shape=(ctx.dims[mode], ctx.K(mode)))
     _check(load_library().ttmc_mode(ctx.handle, mode, _ptrs(U, ctx, skip=mode), yp, _stream()))
     return Y
+
+
+def ttmc_memo_pair(ctx: Ctx, U, U_next: torch.Tensor):
+    """(Y_a, Y_b): the TTMc of mode N-2 with U and of mode N-1 with U[N-2] replaced by U_next, the
+    second from the first's fiber sums (order >= 4)."""
+    N = ctx.order
+    if N < 4:
+        raise ValueError("ttmc_memo_pair needs order >= 4")
+    a, b = N - 2, N - 1
+    Ya = torch.empty((ctx.dims[a], ctx.K(a)), dtype=ctx.ytype, device="cuda")
+    Yb = torch.empty((ctx.dims[b], ctx.K(b)), dtype=ctx.ytype, device="cuda")
+    un = _dev(U_next, torch.float64, "U_next", shape=(ctx.dims[a], ctx.ranks[a]))
+    _check(load_library().ttmc_memo_pair(ctx.handle, _ptrs(U, ctx, skip=a), un,
+                                         _dev(Ya, ctx.ytype, "Y_a"), _dev(Yb, ctx.ytype, "Y_b"), _stream()))
+    return Ya, Yb
 
 
 def qrp_update(ctx: Ctx, mode: int, Y: torch.Tensor, U_out: torch.Tensor | None = None,

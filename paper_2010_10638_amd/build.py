@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIB_DIR, "libsptucker.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["api.hip", "build.hip", "ttmc.hip", "qrp.hip", "core.hip", "completion.hip", "svd.hip"]
+SOURCES = ["api.hip", "build.hip", "ttmc.hip", "memo.hip", "qrp.hip", "core.hip", "completion.hip", "svd.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -58,6 +58,7 @@ void free_ctx(tk_ctx* c) {
     free_events(c);
     free_completion_ws(c);
     free_svd_ws(c);
+    free_memo(c);
     for (int m = 0; m < kMaxOrder; ++m) {
         ModeLayout& ml = c->mode[m];
         void* ps[] = {ml.rows, ml.ptr, ml.pptr, ml.idx, ml.val, ml.chunk_ptr, ml.chunk_row, ml.chunk_slot, ml.split};
@@ -107,7 +108,7 @@ int tucker_init(tk_ctx** out, int order, const int64_t* dims, const int32_t* ran
     if (nnz < 0) return set_error(TK_ERR_ARG, "negative nnz");
     if (nnz >= (int64_t)1 << 31) return set_error(TK_ERR_UNSUPPORTED, "nnz %lld >= 2^31", (long long)nnz);
     if (nnz > 0 && (!coords || !vals)) return set_error(TK_ERR_ARG, "coords/vals is null");
-    if (flags & ~(TK_FLAG_NO_FAT_RULE | TK_FLAG_SVD | TK_FLAG_SVD_LIB))
+    if (flags & ~(TK_FLAG_NO_FAT_RULE | TK_FLAG_SVD | TK_FLAG_SVD_LIB | TK_FLAG_NO_MEMO))
         return set_error(TK_ERR_ARG, "unknown flags 0x%x", flags);
     double log2prod = 0.0;
     for (int t = 0; t < order; ++t) {
@@ -220,6 +221,27 @@ int ttmc_mode(tk_ctx* ctx, int mode, const double* const* U, void* Y, void* stre
     for (int t = 0; t < ctx->N; ++t)
         if (t != mode && (st = convert_factor(ctx, t, U[t], s))) return st;
     st = ttmc_run(ctx, mode, Y, s);
+    ctx->last_stream = s;
+    return st;
+}
+
+int ttmc_memo_pair(tk_ctx* ctx, const double* const* U, const double* U_next, void* Y_a, void* Y_b, void* stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    const int N = ctx->N;
+    if (!U || !U_next || !Y_a || !Y_b) return set_error(TK_ERR_ARG, "U/U_next/Y_a/Y_b is null");
+    for (int t = 0; t < N; ++t)
+        if (t != N - 2 && !U[t]) return set_error(TK_ERR_ARG, "U[%d] is null", t);
+    if ((st = pending_error())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = memo_build(ctx, s))) return st;
+    if (ctx->memo.state != 1)
+        return set_error(TK_ERR_UNSUPPORTED, "shared sums need order >= 4 and the fiber kernel on mode N-2");
+    for (int t = 0; t < N; ++t)
+        if (t != N - 2 && (st = convert_factor(ctx, t, U[t], s))) return st;
+    if ((st = memo_first_run(ctx, Y_a, s))) return st;
+    if ((st = convert_factor(ctx, N - 2, U_next, s))) return st;
+    st = memo_last_run(ctx, Y_b, s);
     ctx->last_stream = s;
     return st;
 }
@@ -348,9 +370,20 @@ int hooi_sweep(tk_ctx* ctx, double* const* U, double* G, double* fit_dev, double
     hipEvent_t* ev = nullptr;
     if (ctx->prof_ev && ctx->prof_used < ctx->prof_cap)
         ev = ctx->prof_ev + (size_t)(ctx->prof_used++) * (4 * N + 2);
+    // modes N-2 and N-1 share the fiber sums of the first N-2 modes when the fibers of mode N-2
+    // hold 4 or more nonzeros on average
+    bool memo = false;
+    if (N >= 4 && !(ctx->flags & TK_FLAG_NO_MEMO)) {
+        if ((st = memo_build(ctx, s))) return st;
+        memo = ctx->memo.state == 1 && ctx->memo.npieces * 4 <= ctx->mode[N - 2].P;
+    }
     for (int n = 0; n < ctx->N; ++n) {
         if (ev) TK_HIP(hipEventRecord(ev[2 * n], s));
-        if ((st = ttmc_run(ctx, n, ctx->ws.y, s, ev ? ev + 2 * N + 2 + 2 * n : nullptr))) return st;
+        hipEvent_t* evm = ev ? ev + 2 * N + 2 + 2 * n : nullptr;
+        if (memo && n == N - 2) st = memo_first_run(ctx, ctx->ws.y, s, evm);
+        else if (memo && n == N - 1) st = memo_last_run(ctx, ctx->ws.y, s, evm);
+        else st = ttmc_run(ctx, n, ctx->ws.y, s, evm);
+        if (st) return st;
         if (ev) TK_HIP(hipEventRecord(ev[2 * n + 1], s));
         st = (ctx->flags & TK_FLAG_SVD) ? svd_run(ctx, n, ctx->ws.y, U[n], s)
                                         : qrp_run(ctx, n, ctx->ws.y, U[n], nullptr, s);

@@ -111,6 +111,20 @@ struct CompletionWs {
     double* part = nullptr;          // loss and core-gradient partials
 };
 
+// Shared partial sums of the last two modes (order >= 4), built on first use by a sweep
+struct MemoWs {
+    int state = 0;                   // 0 not built, 1 built, -1 not applicable to the context
+    int64_t npieces = 0;             // fiber pieces of mode N-2 (fibers cut by chunk starts)
+    int Ks = 0;                      // inner columns: prod_{k < N-2} R_k
+    int nsplit = 1;                  // waves per row of mode N-1
+    int32_t* pid_base = nullptr;     // [nchunks of mode N-2] first piece of each chunk
+    int32_t* pj = nullptr;           // [npieces] i_{N-2} of each piece
+    int32_t* perm = nullptr;         // [npieces] pieces ordered by i_{N-1} (stream order within)
+    int32_t* rptr = nullptr;         // [I_{N-1} + 1] first position of each i_{N-1} in perm
+    void* T = nullptr;               // [npieces][Ks] inner sums, TTMc arithmetic type
+    void* part = nullptr;            // [I_{N-1}][nsplit][K_{N-1}] partial rows (nsplit > 1)
+};
+
 }  // namespace tk
 
 struct tk_ctx {
@@ -127,6 +141,7 @@ struct tk_ctx {
     tk::Workspace ws;
     double* qrp_gaps = nullptr;      // [N * kGramMaxR] relative pivot gaps of each mode's last QRP
     tk::CompletionWs cws;
+    tk::MemoWs memo;
     // SVD factor update: rocBLAS handle and eigen-solver workspace (allocated on first use)
     void* rb = nullptr;
     double* svd_d = nullptr;         // eigenvalues, TK_MAX_KCOLS
@@ -198,8 +213,10 @@ int fill_f64(double* p, int64_t n, double v, hipStream_t s);   // a kernel, not 
 // TTMc (ttmc.hip): uses ctx->Ulp copies
 // ev_main (optional, [2]): events recorded on s around the main TTMc kernel (fix-up excluded);
 // val (optional): values on the mode's padded stream to use instead of the tensor's (same type)
+// memo, pid_base (optional, fiber kernel only): also write the inner sum of every fiber piece to
+// memo[piece][Ks] (pieces in stream order from pid_base[chunk])
 int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main = nullptr,
-             const void* val = nullptr);
+             const void* val = nullptr, void* memo = nullptr, const int32_t* pid_base = nullptr);
 // columns of the factor copy of mode t (16, a multiple of 16 above, or 8 for order >= 4 with
 // every rank <= 8) and the TTMc kernel a mode runs (enum tk_ttmc_kernel); host-only
 int factor_ld(int N, const int32_t* ranks, int t);
@@ -215,6 +232,14 @@ int ttmc_residual_run(tk_ctx* ctx, int mode, void* Y, const float* W, double* pa
 int adjoint_run(tk_ctx* ctx, const void* G, const void* const* U, void* loss, void* gG, void* const* gU,
                 hipStream_t s);
 void free_completion_ws(tk_ctx* ctx);
+// Shared partial sums of modes N-2 and N-1 (memo.hip): applicability, the layout (built once;
+// state -1 when not applicable), mode N-2's TTMc that also writes the fiber sums, and mode N-1's
+// TTMc from them with the current copy of U_{N-2}
+bool memo_applicable(const tk_ctx* ctx);
+int memo_build(tk_ctx* ctx, hipStream_t s);
+void free_memo(tk_ctx* ctx);
+int memo_first_run(tk_ctx* ctx, void* Y, hipStream_t s, hipEvent_t* ev_main = nullptr);
+int memo_last_run(tk_ctx* ctx, void* Y, hipStream_t s, hipEvent_t* ev_main = nullptr);
 
 // QRP (qrp.hip): Y -> U (FP64) and the low-precision copy ctx->Ulp[mode]
 int qrp_run(tk_ctx* ctx, int mode, const void* Y, double* U, int32_t* piv, hipStream_t s);

@@ -671,6 +671,10 @@ struct FiberArgs {
     int32_t Rf;
     int32_t Ks;                    // prod_inner R
     int32_t tw;                    // staged values per nonzero: sum_inner R (<= kFiberTile)
+    // optional: the inner sum of every fiber piece (a fiber, or its part inside one chunk) is
+    // also written to memo[piece][Ks], pieces numbered in stream order from pid_base[chunk]
+    void* memo;
+    const int32_t* pid_base;
 };
 
 constexpr int kFiberTile = 32;
@@ -730,7 +734,7 @@ __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
     i4v i1 = {0, 0, 0, 0}, i2 = {0, 0, 0, 0};
     AT x1 = AT(0), x2 = AT(0);
     uint4 raw[NM1][NV];
-    auto load_idx = [&](int p, i4v& ix, AT& xv) {
+    auto load_idx = [&](int p, i4v& ix, AT& xv) __attribute__((always_inline)) {
         const int qq = p + lane;
         const bool v = qq < q1;
         const int qc = v ? qq : q1 - 1;
@@ -741,7 +745,7 @@ __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
     // the fiber-mode row is read only by a nonzero that starts a fiber (the walk reads it there
     // alone); last_f: fiber index of the previous batch's last nonzero (-1 at the chunk start)
     int last_f = -1;
-    auto load_rows = [&](const i4v ix) {
+    auto load_rows = [&](const i4v ix) __attribute__((always_inline)) {
         int prevf = __shfl_up(ix[NM1 - 1], 1);
         if (lane == 0) prevf = last_f;
         last_f = __builtin_amdgcn_readlane(ix[NM1 - 1], 63);
@@ -756,7 +760,17 @@ __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
             }
         }
     };
-    auto fold = [&]() {
+    // fiber sums: this lane's place in the next piece's row (a per-lane pointer keeps it out of
+    // the scalar registers, which the wide instances have none to spare of)
+    const bool has_memo = f.memo != nullptr && q1 > q0;   // an empty chunk holds no piece
+    AT* mlane = has_memo ? (AT*)f.memo + (int64_t)f.pid_base[ch] * f.Ks + lane : nullptr;
+    auto fold = [&]() __attribute__((always_inline)) {
+        if (has_memo) {   // wave-uniform
+#pragma unroll
+            for (int j = 0; j < KSL; ++j)
+                if (lane + 64 * j < f.Ks) mlane[64 * j] = sacc[j];
+            mlane += f.Ks;
+        }
 #pragma unroll
         for (int j = 0; j < KSL; ++j) {
 #pragma unroll
@@ -764,7 +778,7 @@ __global__ __launch_bounds__(256) void k_ttmc_fiber(TtmcArgs a, FiberArgs f) {
             sacc[j] = AT(0);
         }
     };
-    auto flush_row = [&]() {
+    auto flush_row = [&]() __attribute__((always_inline)) {
         const bool owner = (srow != s0) || (slot < 0);
         // select the base as an integer (a pointer select here was lowered through scratch)
         const uint64_t base = owner ? (uint64_t)(uintptr_t)a.Y : (uint64_t)(uintptr_t)a.carry;
@@ -1058,7 +1072,8 @@ int ttmc_residual_run(tk_ctx* ctx, int mode, void* Y, const float* W, double* pa
     return run_fixup(ctx, ml, Y, s);
 }
 
-int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main, const void* val) {
+int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main, const void* val, void* memo,
+             const int32_t* pid_base) {
     const ModeLayout& ml = ctx->mode[mode];
     const int N = ctx->N;
     const int64_t In = ctx->dims[mode];
@@ -1091,8 +1106,11 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
         }
         fa.Rf = a.R[N - 2];
         fa.tw = off;
+        fa.memo = memo;
+        fa.pid_base = pid_base;
         fiber_ok = small;   // always true when ttmc_kernel_for chose this kernel
     }
+    if (memo && !fiber_ok) return set_error(TK_ERR_ARG, "fiber sums requested from a mode without the fiber kernel");
     if (ev_main) TK_HIP(hipEventRecord(ev_main[0], s));
     if (mfma_ok) {
         if (ctx->dtype == TK_F64) {

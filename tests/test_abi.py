@@ -56,8 +56,7 @@ def _init(lib, order=3, dims=(5, 6, 7), ranks=(2, 2, 2), nnz=0, dtype=1, flags=0
     (dict(nnz=1 << 31), 5),
     (dict(nnz=10), 1),                                   # coords/vals null
     (dict(flags=0x80), 1),
-    (dict(flags=0x80), 1),
-    (dict(flags=0x8), 1),
+    (dict(flags=0x10), 1),                               # the first bit past TK_FLAG_NO_MEMO
     (dict(ranks=(6, 2, 2)), 1),                          # R_1 > I_1
     (dict(dims=(5, 0, 7)), 1),
     (dict(dims=(2000,) * 3, ranks=(65, 65, 65)), 5),     # K_n = 4225 > 4096

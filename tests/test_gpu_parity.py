@@ -30,9 +30,9 @@ def dev_list(U):
     return [torch.from_numpy(np.ascontiguousarray(u, dtype=np.float64)).cuda() for u in U]
 
 
-def make(tk, w, dtype, fat_rule=True):
+def make(tk, w, dtype, fat_rule=True, memo=True):
     c, v = to_dev(w.coords, w.vals)
-    return tk.tucker_init(c, v, w.dims, w.ranks, dtype=dtype, fat_rule=fat_rule)
+    return tk.tucker_init(c, v, w.dims, w.ranks, dtype=dtype, fat_rule=fat_rule, memo=memo)
 
 
 def with_duplicates(w, k=37, seed=0):
@@ -522,6 +522,77 @@ def test_hooi_order4_f32(tk):
     U = dev_list(w.U_init)
     fits = [tk.hooi_sweep(ctx, U, sync_fit=True)[1] for _ in range(w.sweeps)]
     np.testing.assert_allclose(fits, fo, rtol=1e-5)
+
+
+# The last two modes' TTMc with shared fiber sums: (dims, ranks, nnz, what it exercises)
+MEMO_CASES = [
+    ([400, 300, 60, 9], [8, 8, 8, 8], 30000, "64 inner columns, about 55 nonzeros per fiber"),
+    ([200, 150, 3, 2], [4, 5, 3, 2], 40000, "6 fibers of about 6,700 nonzeros, cut by chunk starts"),
+    ([50, 40, 30, 20], [4, 12, 12, 16], 20000, "48 inner columns, R_{N-2} = 12, R_{N-1} = 16"),
+    ([12, 10, 9, 8, 7], [2, 3, 2, 2, 2], 2500, "order 5: three inner modes"),
+    ([30, 20, 500, 400], [3, 3, 4, 5], 20000, "mostly one-nonzero fibers"),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("case", range(len(MEMO_CASES)), ids=[c[3][:28] for c in MEMO_CASES])
+def test_ttmc_memo_pair(tk, dtype, case):
+    """Y_(N-2) with U and Y_(N-1) with U_{N-2} replaced (the second from the first's fiber sums)
+    against the oracle's TTMc of each mode."""
+    dims, ranks, nnz, _ = MEMO_CASES[case]
+    w = synth.small_uniform(300 + case, dims, ranks, nnz)
+    N = len(dims)
+    a, b = N - 2, N - 1
+    ctx = make(tk, w, dtype)
+    rng = np.random.default_rng(400 + case)
+    Unext = rng.standard_normal((dims[a], ranks[a]))
+    Ya, Yb = tk.ttmc_memo_pair(ctx, dev_list(w.U_init), torch.from_numpy(Unext).cuda())
+    U2 = list(w.U_init)
+    U2[a] = Unext
+    for Y, mode, U in ((Ya, a, w.U_init), (Yb, b, U2)):
+        Y = Y.double().cpu().numpy()
+        Yo = oracle.ttmc(w.coords, w.vals, dims, ranks, mode, U)
+        assert rel_fro(Y, Yo) <= TOL_Y[dtype], (mode, rel_fro(Y, Yo))
+        Yc = oracle.ttmc(w.coords, cast_vals(w.vals, dtype), dims, ranks, mode, cast_inputs(U, dtype))
+        assert rel_fro(Y, Yc) <= (1e-13 if dtype == "f64" else 2e-6), (mode, rel_fro(Y, Yc))
+    # the fiber table is kept: a second call with other factors gives their products
+    Unext2 = rng.standard_normal((dims[a], ranks[a]))
+    _, Yb2 = tk.ttmc_memo_pair(ctx, dev_list(w.U_init), torch.from_numpy(Unext2).cuda())
+    U2[a] = Unext2
+    Yo = oracle.ttmc(w.coords, w.vals, dims, ranks, b, U2)
+    assert rel_fro(Yb2.double().cpu().numpy(), Yo) <= TOL_Y[dtype]
+
+
+def test_ttmc_memo_pair_unsupported(tk):
+    """Order 3 has no fiber kernel: the C ABI refuses the call before any launch (the binding
+    refuses it before calling)."""
+    import ctypes
+    from paper_2010_10638_amd import binding
+    w = synth.small_uniform(320, [30, 20, 10], [3, 3, 3], 500)
+    ctx = make(tk, w, "f32")
+    U = dev_list(w.U_init)
+    with pytest.raises(ValueError):
+        tk.ttmc_memo_pair(ctx, U, U[1])
+    Y = torch.empty(1 << 12, dtype=torch.float32, device="cuda")
+    up = (ctypes.c_void_p * 3)(*[u.data_ptr() for u in U])
+    st = binding.load_library().ttmc_memo_pair(ctx.handle, up, ctypes.c_void_p(U[1].data_ptr()),
+                                               ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(Y.data_ptr()), None)
+    assert st == binding.TK_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_hooi_sweeps_memo(tk, dtype, tol):
+    """Sweeps whose last two modes share the fiber sums (about 55 nonzeros per fiber) against the
+    oracle's fits, and against the same sweeps without the sharing."""
+    w = synth.small_uniform(330, [400, 300, 60, 9], [8, 8, 8, 8], 30000, sweeps=3)
+    Uo, Go, fo, _ = oracle.hooi(w.coords, w.vals, w.dims, w.ranks, w.U_init, w.sweeps)
+    fits = {}
+    for memo in (True, False):
+        ctx = make(tk, w, dtype, memo=memo)
+        U = dev_list(w.U_init)
+        fits[memo] = [tk.hooi_sweep(ctx, U, sync_fit=True)[1] for _ in range(w.sweeps)]
+        np.testing.assert_allclose(fits[memo], fo, rtol=tol)
+    np.testing.assert_allclose(fits[True], fits[False], rtol=tol)
 
 
 def test_reconstruct_parity(tk):
