@@ -114,7 +114,11 @@ template <typename AT, typename ST> __device__ inline AT to_at(const ST* p, int6
     else return (AT)p[i];
 }
 
-// one wave per (row, split); lane l owns inner columns l + 64 j (j < KSL), with R <= RF sums each
+// one wave per (row, split); lane l owns inner columns l + 64 j (j < KSL), with R <= RF sums each.
+// Pieces are taken eight at a time: their numbers, rows of U and rows of T are all requested
+// before the products (a piece alone is a chain of three dependent loads).
+constexpr int kMemoGroup = 8;
+
 template <typename AT, typename ST, int KSL, int RF>
 __global__ __launch_bounds__(64) void k_memo_rows(MemoRowArgs a) {
     const int lane = threadIdx.x;
@@ -130,19 +134,30 @@ __global__ __launch_bounds__(64) void k_memo_rows(MemoRowArgs a) {
     for (int j = 0; j < KSL; ++j)
 #pragma unroll
         for (int r = 0; r < RF; ++r) acc[j][r] = AT(0);
-    for (int k = lo; k < hi; ++k) {
-        const int p = a.perm[k];
-        const ST* urow = U + (int64_t)a.pj[p] * a.ld;
-        AT u[RF];
+    for (int k0 = lo; k0 < hi; k0 += kMemoGroup) {
+        int p[kMemoGroup];
 #pragma unroll
-        for (int r = 0; r < RF; ++r) u[r] = (r < a.R) ? to_at<AT, ST>(urow, r) : AT(0);
+        for (int g = 0; g < kMemoGroup; ++g) p[g] = a.perm[min(k0 + g, hi - 1)];
+        AT u[kMemoGroup][RF], t[kMemoGroup][KSL];
 #pragma unroll
-        for (int j = 0; j < KSL; ++j) {
-            const int cs = lane + 64 * j;
-            const AT t = (cs < a.Ks) ? T[(int64_t)p * a.Ks + cs] : AT(0);
+        for (int g = 0; g < kMemoGroup; ++g) {
+            const bool live = k0 + g < hi;
+            const ST* urow = U + (int64_t)a.pj[p[g]] * a.ld;
 #pragma unroll
-            for (int r = 0; r < RF; ++r) acc[j][r] += t * u[r];
+            for (int r = 0; r < RF; ++r) u[g][r] = (live && r < a.R) ? to_at<AT, ST>(urow, r) : AT(0);
+#pragma unroll
+            for (int j = 0; j < KSL; ++j) {
+                const int cs = lane + 64 * j;
+                t[g][j] = (cs < a.Ks) ? T[(int64_t)p[g] * a.Ks + cs] : AT(0);
+            }
         }
+        // pieces in order (the sum order of the plain loop)
+#pragma unroll
+        for (int g = 0; g < kMemoGroup; ++g)
+#pragma unroll
+            for (int j = 0; j < KSL; ++j)
+#pragma unroll
+                for (int r = 0; r < RF; ++r) acc[j][r] += t[g][j] * u[g][r];
     }
     AT* dst = (AT*)a.out + ((a.nsplit == 1) ? i * a.K : (i * a.nsplit + sp) * a.K);
 #pragma unroll

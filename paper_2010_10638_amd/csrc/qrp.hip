@@ -22,6 +22,8 @@
 // Householder QRP in one workgroup: exact trailing-norm recompute, first-maximum pivot,
 // v = x + sgn(x_0)||x|| e_1.
 // Route 2 (fat Y, K_n > I_n) - the same kernel on Y Y^T (I_n x I_n), as Sec. III-D prescribes.
+#include <hip/hip_cooperative_groups.h>
+
 #include "internal.h"
 #include "atb.h"
 
@@ -690,10 +692,259 @@ __global__ __launch_bounds__(1024) void k_house_qrp(const YT* __restrict__ src, 
     house_qrp_body<YT, LT>(src, A, m, n, R, V, w, beta_s, perm, U, Ulp, ldlp, piv_out, gaps);
 }
 
+// The same Householder QRP spread over the whole grid (cooperative launch, grid barriers between
+// phases), for matrices too large for one workgroup to stream quickly.  Block b owns rows
+// [b slab, (b+1) slab).  Per step j:
+//   1. each block: partial squared norms of columns j..n-1 over its rows >= j;      barrier
+//   2. the column totals, each block a share of the columns (fixed addition order);  barrier
+//   3. block 0: first maximum, runner-up, the swap in perm; the pivot, its squared norm and
+//      x0 = A[j][p] (read before any swap) to ctl;                                      barrier
+//   4. each block: swap columns j and p in its rows, v = its part of x + sgn(x0) alpha e_j, with
+//      ||v||^2 = 2 alpha^2 + 2 |x0| alpha; partial v^T A over columns j..n-1;          barrier
+//   5. w = beta v^T A, totals spread as in 2;                                           barrier
+//   6. each block: A -= v w^T on its rows.
+// Q = H_0 ... H_{R-1} [I; 0] the same way (partials, totals, update), then the copies.
+// Every block takes every barrier (all loop bounds and branch conditions are read from the same
+// reduced values), and with a flag the whole grid returns at once when it is clear.
+namespace cg = cooperative_groups;
+
+template <typename YT, typename LT>
+struct HouseGridArgs {
+    const YT* src;              // Y to copy into A, or null (A already filled)
+    double* A;                  // m x n, row-major, in place
+    int64_t m;
+    int n, R;
+    double* V;                  // m x R reflectors
+    double* w;                  // max(n, R)
+    double* beta_s;             // R
+    int32_t* perm;              // n
+    double* U;                  // m x R
+    LT* Ulp;
+    int ldlp;
+    int32_t* piv_out;           // R, or null
+    double* gaps;               // R, or null
+    const int32_t* flag;        // run only when *flag != 0, or null (always run)
+    double* part;               // gridDim.x x max(n, R^2) partials
+    double* ctl;                // n: a copy of the row of A at the current step
+    int64_t slab;               // rows per block
+};
+
+constexpr int kHouseGridT = 256;
+
+// out[c] for c in [c0, n): sum over the block's rows i in [lo, hi) of f(i, c); lane = column,
+// wave = row stride; the waves' partials added in order through LDS
+template <typename F>
+__device__ inline void slab_column_sums(int64_t lo, int64_t hi, int c0, int n, double* red, double* out, F f) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = kHouseGridT / 64;
+    for (int cb = c0; cb < n; cb += 64) {
+        const int c = cb + lane;
+        double acc = 0.0;
+        if (c < n)
+            for (int64_t i = lo + wv; i < hi; i += NW) acc += f(i, c);
+        red[wv * 64 + lane] = acc;
+        __syncthreads();
+        if (tid < 64 && c < n) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) t += red[k * 64 + lane];
+            out[c] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// out[c] = scale * sum_{k < nb} part[k][c] for the columns c = c0 + b, c0 + b + nb, ... < n of
+// block b: thread t adds the partials k = t, t + 256, ... in order, then the threads' sums are
+// added in a fixed tree (wave shuffles, then the waves in order)
+__device__ inline void grid_column_totals(const double* part, int pw, int nb, int c0, int n, double scale,
+                                          double* red, double* out) {
+    const int tid = threadIdx.x;
+    for (int c = c0 + (int)blockIdx.x; c < n; c += nb) {
+        double t = 0.0;
+        for (int k = tid; k < nb; k += kHouseGridT) t += part[(int64_t)k * pw + c];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if ((tid & 63) == 0) red[tid >> 6] = t;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < kHouseGridT / 64; ++k) s += red[k];
+            out[c] = scale * s;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename YT, typename LT>
+__global__ __launch_bounds__(kHouseGridT) void k_house_qrp_grid(HouseGridArgs<YT, LT> a) {
+    if (a.flag && *a.flag == 0) return;   // every block reads the same flag: all return together
+    cg::grid_group grid = cg::this_grid();
+    __shared__ double red[kHouseGridT];
+    __shared__ double bv_s[kHouseGridT / 64], b2_s[kHouseGridT / 64];
+    __shared__ int bp_s[kHouseGridT / 64];
+    __shared__ double s_piv[3];             // pivot, its squared norm, x0
+    __shared__ double s_T[kGramMaxR][kGramMaxR], s_M[kGramMaxR][kGramMaxR], s_G[kGramMaxR * kGramMaxR];
+    const int tid = threadIdx.x, nb = gridDim.x, b = blockIdx.x;
+    const int n = a.n, R = a.R;
+    const int64_t m = a.m;
+    const int64_t r0 = min(m, (int64_t)b * a.slab), r1 = min(m, r0 + a.slab);
+    const int pw = max(n, R * R);
+    double* mypart = a.part + (int64_t)b * pw;
+    double* rowbuf = a.ctl;                 // row j of A as it stands before step j (n values)
+    if (a.src)
+        for (int64_t e = r0 * n + tid; e < r1 * n; e += kHouseGridT) a.A[e] = yld(a.src, e);
+    if (b == 0)
+        for (int c = tid; c < n; c += kHouseGridT) a.perm[c] = c;
+    __syncthreads();
+    if (r0 <= 0 && 0 < r1)
+        for (int c = tid; c < n; c += kHouseGridT) rowbuf[c] = a.A[c];
+    for (int j = 0; j < R; ++j) {
+        // 1. partial squared norms
+        slab_column_sums(max(r0, (int64_t)j), r1, j, n, red, mypart, [&](int64_t i, int c) {
+            const double x = a.A[i * n + c];
+            return x * x;
+        });
+        grid.sync();
+        // 2. column totals, spread over the blocks
+        grid_column_totals(a.part, pw, nb, j, n, 1.0, red, a.w);
+        grid.sync();
+        // 3. every block: pivot (first maximum) and runner-up over the totals, the same result on
+        // each; x0 from the copy of row j
+        {
+            double bv = -1.0, b2 = -1.0;
+            int bp = n;
+            for (int c = j + tid; c < n; c += kHouseGridT) {   // ascending: first maximum kept
+                const double t = a.w[c];
+                if (t > bv) { b2 = fmax(b2, bv); bv = t; bp = c; }
+                else b2 = fmax(b2, t);
+            }
+            for (int o = 1; o < 64; o <<= 1) {
+                const double v2 = __shfl_xor(bv, o), s2 = __shfl_xor(b2, o);
+                const int p2 = __shfl_xor(bp, o);
+                const bool take = v2 > bv || (v2 == bv && p2 < bp);
+                b2 = fmax(fmax(b2, s2), take ? bv : v2);
+                if (take) { bv = v2; bp = p2; }
+            }
+            if ((tid & 63) == 0) { bv_s[tid >> 6] = bv; b2_s[tid >> 6] = b2; bp_s[tid >> 6] = bp; }
+            __syncthreads();
+            if (tid == 0) {
+                double best = bv_s[0], second = b2_s[0];
+                int pb = bp_s[0];
+                for (int k = 1; k < kHouseGridT / 64; ++k) {
+                    const bool take = bv_s[k] > best || (bv_s[k] == best && bp_s[k] < pb);
+                    second = fmax(fmax(second, b2_s[k]), take ? best : bv_s[k]);
+                    if (take) { best = bv_s[k]; pb = bp_s[k]; }
+                }
+                if (pb >= n) pb = j;   // no comparable norm (NaN): keep the column in place (alpha NaN)
+                if (b == 0) {
+                    if (a.gaps) a.gaps[j] = (second < 0.0) ? 1.0 : (best > 0.0 ? (best - second) / best : 0.0);
+                    const int t = a.perm[j]; a.perm[j] = a.perm[pb]; a.perm[pb] = t;
+                }
+                s_piv[0] = (double)pb;
+                s_piv[1] = best;
+                s_piv[2] = rowbuf[pb];
+            }
+            __syncthreads();
+        }
+        // 4. swap, reflector, partial v^T A
+        const int p = (int)s_piv[0];
+        const double alpha = sqrt(s_piv[1]), x0 = s_piv[2];
+        if (p != j)
+            for (int64_t i = r0 + tid; i < r1; i += kHouseGridT) {
+                const double t = a.A[i * n + j];
+                a.A[i * n + j] = a.A[i * n + p];
+                a.A[i * n + p] = t;
+            }
+        if (alpha == 0.0) {   // the same on every block
+            if (b == 0 && tid == 0) a.beta_s[j] = 0.0;
+            for (int64_t i = r0 + tid; i < r1; i += kHouseGridT) a.V[i * R + j] = 0.0;
+            grid.sync();   // every block has read this step's copy of row j
+            if (r0 <= j + 1 && j + 1 < r1)
+                for (int c = tid; c < n; c += kHouseGridT) rowbuf[c] = a.A[(int64_t)(j + 1) * n + c];
+            continue;
+        }
+        const double sg = (x0 >= 0.0 ? 1.0 : -1.0);
+        for (int64_t i = r0 + tid; i < r1; i += kHouseGridT) {
+            double v = 0.0;
+            if (i >= j) {
+                v = a.A[i * n + j];
+                if (i == j) v += sg * alpha;
+            }
+            a.V[i * R + j] = v;
+        }
+        const double beta = 2.0 / (2.0 * alpha * alpha + 2.0 * fabs(x0) * alpha);
+        if (b == 0 && tid == 0) a.beta_s[j] = beta;
+        __syncthreads();
+        slab_column_sums(max(r0, (int64_t)j), r1, j, n, red, mypart,
+                         [&](int64_t i, int c) { return a.V[i * R + j] * a.A[i * n + c]; });
+        grid.sync();
+        // 5. w = beta v^T A, spread over the blocks
+        grid_column_totals(a.part, pw, nb, j, n, beta, red, a.w);
+        grid.sync();
+        // 6. A -= v w^T on this block's rows >= j; the owner of row j + 1 copies it for step j + 1
+        for (int64_t i = max(r0, (int64_t)j); i < r1; ++i) {
+            const double vi = a.V[i * R + j];
+            for (int c = j + tid; c < n; c += kHouseGridT) a.A[i * n + c] -= vi * a.w[c];
+        }
+        __syncthreads();   // the next step's column sums read these rows from other threads
+        if (r0 <= j + 1 && j + 1 < r1)
+            for (int c = tid; c < n; c += kHouseGridT) rowbuf[c] = a.A[(int64_t)(j + 1) * n + c];
+    }
+    // Q = H_0 ... H_{R-1} [I; 0] = [I; 0] - V T V_top^T (compact WY form: T upper triangular with
+    // T_jj = beta_j, T[0:j, j] = -beta_j T[0:j, 0:j] (V[:, 0:j]^T v_j); V_top = the first R rows)
+    slab_column_sums(r0, r1, 0, R * R, red, mypart,
+                     [&](int64_t i, int c) { return a.V[i * R + c / R] * a.V[i * R + c % R]; });
+    grid.sync();
+    // every block: the Gram of V (blocks added in order), T and M = T V_top^T, the same on each
+    for (int e = tid; e < R * R; e += kHouseGridT) {
+        double g = 0.0;
+        for (int k = 0; k < nb; ++k) g += a.part[(int64_t)k * pw + e];
+        s_G[e] = g;
+    }
+    for (int e = tid; e < kGramMaxR * kGramMaxR; e += kHouseGridT) s_T[e / kGramMaxR][e % kGramMaxR] = 0.0;
+    __syncthreads();
+    for (int j = 0; j < R; ++j) {   // column j of T from columns 0..j-1 (thread i: entry i)
+        const double bj = a.beta_s[j];
+        if (tid < j) {
+            double t = 0.0;
+            for (int k = tid; k < j; ++k) t += s_T[tid][k] * s_G[k * R + j];
+            s_T[tid][j] = -bj * t;
+        } else if (tid == j) {
+            s_T[j][j] = bj;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < R * R; e += kHouseGridT) {
+        const int r = e / R, c = e % R;
+        double t = 0.0;
+        for (int k = r; k < R; ++k) t += s_T[r][k] * a.V[(int64_t)c * R + k];   // V_top[c][k]
+        s_M[r][c] = t;
+    }
+    __syncthreads();
+    for (int64_t e = r0 * R + tid; e < r1 * R; e += kHouseGridT) {
+        const int64_t i = e / R;
+        const int c = (int)(e % R);
+        double u = (i == c) ? 1.0 : 0.0;
+        for (int k = 0; k < R; ++k) u -= a.V[i * R + k] * s_M[k][c];
+        a.U[e] = u;
+    }
+    __syncthreads();
+    for (int64_t e = r0 * a.ldlp + tid; e < r1 * a.ldlp; e += kHouseGridT) {
+        const int64_t i = e / a.ldlp;
+        const int c = (int)(e % a.ldlp);
+        const double u = (c < R) ? a.U[i * R + c] : 0.0;
+        if constexpr (sizeof(LT) == 8) a.Ulp[e] = u;
+        else if constexpr (sizeof(LT) == 4) a.Ulp[e] = (float)u;
+        else a.Ulp[e] = f32_to_bf16((float)u);
+    }
+    if (b == 0 && a.piv_out && tid < R) a.piv_out[tid] = a.perm[tid];
+}
+
 // U = Y[:, piv] M and its low-precision copy; ldlp consecutive threads share a row, one output
 // column each (columns R..ldlp-1 of the copy are zeroed).
-// After a breakdown (device flag set) workgroup 0 runs the Householder QRP on Y instead and the
-// others exit.
+// After a breakdown (device flag set) workgroup 0 runs the Householder QRP on Y instead (small Y)
+// or the grid-wide kernel launched after this one does (large Y), and the others exit.
 template <typename YT, typename LT>
 __global__ __launch_bounds__(1024) void k_form_u(const YT* __restrict__ Y, int64_t m, int n, int R,
                                                 const int32_t* __restrict__ pivw,
@@ -703,9 +954,10 @@ __global__ __launch_bounds__(1024) void k_form_u(const YT* __restrict__ Y, int64
                                                 double* __restrict__ A, double* __restrict__ V,
                                                 double* __restrict__ wv, double* __restrict__ beta_s,
                                                 int32_t* __restrict__ perm, int32_t* __restrict__ piv_out,
-                                                double* __restrict__ gaps) {
-    if (*flag) {
-        if (blockIdx.x == 0) house_qrp_body<YT, LT>(Y, A, m, n, R, V, wv, beta_s, perm, U, Ulp, ldlp, piv_out, gaps);
+                                                double* __restrict__ gaps, int fallback_here) {
+    if (*flag) {   // fallback_here = 0: the grid-wide kernel, launched next, takes it
+        if (fallback_here && blockIdx.x == 0)
+            house_qrp_body<YT, LT>(Y, A, m, n, R, V, wv, beta_s, perm, U, Ulp, ldlp, piv_out, gaps);
         return;
     }
     __shared__ double sM[32 * 32];
@@ -738,8 +990,18 @@ struct QrpPlan {
     int64_t rows2;
     // offsets into the FP64 workspace (in doubles)
     int64_t o_part, o_C, o_L, o_R11, o_Rinv, o_part2, o_G2, o_M, o_A, o_V, o_w, o_beta;
+    bool grid;       // the Householder QRP (route 1/2, route-0 fallback) runs grid-wide
+    int64_t o_hpart, o_hctl;
     int64_t total;
 };
+
+// Householder inputs of at least this many entries take the grid-wide kernel, with at least
+// TK_HOUSE_ROWS rows per block
+constexpr int64_t kHouseGridMin = 1 << 18;
+constexpr int kHouseGridMaxB = 256;
+#ifndef TK_HOUSE_ROWS
+#define TK_HOUSE_ROWS 32
+#endif
 
 QrpPlan plan(const tk_ctx* ctx, int mode) {
     QrpPlan p{};
@@ -786,8 +1048,47 @@ QrpPlan plan(const tk_ctx* ctx, int mode) {
     p.o_V = off; off += hm * R;
     p.o_w = off; off += std::max<int64_t>(hn, R);
     p.o_beta = off; off += R;
+    p.grid = hm * hn >= kHouseGridMin && R <= kGramMaxR;
+    if (p.grid) {
+        p.o_hpart = off; off += (int64_t)kHouseGridMaxB * std::max<int64_t>(hn, (int64_t)R * R);
+        p.o_hctl = off; off += hn;
+    }
     p.total = off;
     return p;
+}
+
+// The grid-wide Householder QRP on (Y or A already filled); gated by flag when not null
+template <typename YT, typename LT>
+int launch_house_grid(const tk_ctx* ctx, const QrpPlan& p, const YT* src, double* W, int32_t* perm, double* U,
+                      LT* Ulp, int ldlp, int32_t* piv, double* gaps, const int32_t* flag, hipStream_t s) {
+    auto kern = k_house_qrp_grid<YT, LT>;
+    int occ = 0;
+    TK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, kHouseGridT, 0));
+    const int64_t want = std::min<int64_t>({(int64_t)kHouseGridMaxB, (int64_t)std::max(ctx->ncu, 1) * std::max(occ, 1),
+                                            (p.m + TK_HOUSE_ROWS - 1) / TK_HOUSE_ROWS});
+    const int nb = (int)std::max<int64_t>(1, want);
+    HouseGridArgs<YT, LT> a{};
+    a.src = src;
+    a.A = W + p.o_A;
+    a.m = p.m;
+    a.n = p.n;
+    a.R = p.R;
+    a.V = W + p.o_V;
+    a.w = W + p.o_w;
+    a.beta_s = W + p.o_beta;
+    a.perm = perm;
+    a.U = U;
+    a.Ulp = Ulp;
+    a.ldlp = ldlp;
+    a.piv_out = piv;
+    a.gaps = gaps;
+    a.flag = flag;
+    a.part = W + p.o_hpart;
+    a.ctl = W + p.o_hctl;
+    a.slab = (p.m + nb - 1) / nb;
+    void* args[] = {&a};
+    TK_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)nb), dim3(kHouseGridT), args, 0, s));
+    return TK_OK;
 }
 
 template <typename YT, typename LT>
@@ -841,8 +1142,9 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
         // U = Y[:, piv] M, or (flag set) the Householder fallback on Y in workgroup 0
         k_form_u<YT, LT><<<cdiv(p.m * ldlp, 1024), 1024, 0, s>>>(Y, p.m, p.n, p.R, pivw, W + p.o_M, flag, U, Ulp, ldlp,
                                                              W + p.o_A, W + p.o_V, W + p.o_w, W + p.o_beta, perm, piv,
-                                                             gaps);
+                                                             gaps, p.grid ? 0 : 1);
         TK_LAUNCH_CHECK("k_form_u");
+        if (p.grid) return launch_house_grid<YT, LT>(ctx, p, Y, W, perm, U, Ulp, ldlp, piv, gaps, flag, s);
         return TK_OK;
     }
     // Householder routes: gaps for the first kGramMaxR steps
@@ -855,6 +1157,8 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
         k_syrk_rows<YT><<<cdiv(I * I, 256), 256, 0, s>>>(Y, (int)I, (int)K, W + p.o_A);
         TK_LAUNCH_CHECK("k_syrk_rows");
     }
+    if (p.grid)
+        return launch_house_grid<YT, LT>(ctx, p, p.route == 2 ? nullptr : Y, W, perm, U, Ulp, ldlp, piv, hgaps, nullptr, s);
     k_house_qrp<YT, LT><<<1, 1024, 0, s>>>(p.route == 2 ? nullptr : Y, W + p.o_A, p.m, p.n, p.R, W + p.o_V, W + p.o_w,
                                            W + p.o_beta, perm, U, Ulp, ldlp, piv, hgaps);
     TK_LAUNCH_CHECK("k_house_qrp");

@@ -329,6 +329,59 @@ def test_qrp_rank_deficient_fallback(tk):
     np.testing.assert_allclose(U[:, :3] @ (U[:, :3].T @ Y), Y, atol=1e-9 * np.abs(Y).max())
 
 
+def test_qrp_fallback_grid_rank_deficient(tk):
+    """As above with a Y of 5,000 x 64 entries (past the size at which the Householder QRP runs on
+    the whole grid): the fallback after the Gram route's breakdown on the grid-wide kernel."""
+    rng = np.random.default_rng(5)
+    dims, ranks = [5000, 8, 8], [5, 8, 8]
+    w = synth.small_uniform(9, dims, ranks, 100)
+    ctx = make(tk, w, "f64")
+    Y = rng.standard_normal((5000, 3)) @ rng.standard_normal((3, 64))
+    U, piv = tk.qrp_update(ctx, 0, torch.from_numpy(Y).cuda())
+    U = U.cpu().numpy()
+    Ue, pe = oracle.factor(Y, 5)
+    assert piv.cpu().numpy()[:3].tolist() == pe[:3].tolist()
+    np.testing.assert_allclose(U.T @ U, np.eye(5), atol=1e-12)
+    np.testing.assert_allclose(U[:, :3] @ (U[:, :3].T @ Y), Y, atol=1e-9 * np.abs(Y).max())
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_qrp_fallback_grid_dominant_direction(tk, dtype):
+    """A full-rank Y whose leading direction is 1e7 times the rest (the shape HOOI reaches on a
+    tensor with a large mean): the Gram's Schur complements fall under 1e-12 of its diagonal, so
+    the Gram route hands over to the grid-wide Householder QRP on Y, whose pivots, factor and
+    pivot gaps match the oracle's."""
+    rng = np.random.default_rng(6)
+    m, K, R = 5000, 512, 8
+    dims, ranks = [m, 8, 64], [R, 8, 64]
+    w = synth.small_uniform(9, dims, ranks, 100)
+    ctx = make(tk, w, dtype)
+    Y = rng.standard_normal((m, K)) + 1e7 * np.outer(rng.random(m), rng.random(K))
+    if dtype == "f32":
+        Y = Y.astype(np.float32).astype(np.float64)
+    yt = torch.float64 if dtype == "f64" else torch.float32
+    U, piv = tk.qrp_update(ctx, 0, torch.from_numpy(Y).to(yt).cuda())
+    Ue, pe, ge = oracle.factor(Y, R, gaps=True)
+    assert piv.cpu().numpy().tolist() == pe.tolist()
+    # the columns after the first are set by the small part of Y: error about eps * 1e7 * ||Y|| / sigma
+    np.testing.assert_allclose(U.cpu().numpy(), Ue, atol=1e-7)
+    np.testing.assert_allclose(np.array(tk.qrp_gaps(ctx, 0)), ge, rtol=1e-5, atol=1e-8)
+
+
+def test_qrp_fat_grid(tk):
+    """Fat Y (600 x 1000): the Householder QRP of Y Y^T (600 x 600) on the grid-wide kernel,
+    pivots, factor and gaps against the oracle."""
+    dims, ranks = [600, 40, 25], [8, 40, 25]
+    w = synth.small_uniform(210, dims, ranks, 30000)
+    ctx = make(tk, w, "f64")
+    Yo = oracle.ttmc(w.coords, w.vals, dims, ranks, 0, w.U_init)
+    U, piv = tk.qrp_update(ctx, 0, torch.from_numpy(Yo).cuda())
+    Ue, pe, ge = oracle.factor(Yo, 8, fat_rule=True, gaps=True)
+    assert piv.cpu().numpy().tolist() == pe.tolist()
+    np.testing.assert_allclose(U.cpu().numpy(), Ue, atol=1e-10)
+    np.testing.assert_allclose(np.array(tk.qrp_gaps(ctx, 0)), ge, rtol=1e-8, atol=1e-12)
+
+
 @pytest.mark.parametrize("K", [64, 256])
 def test_qrp_tied_norms(tk, K):
     """Columns 3 and 7 of Y have exactly equal norms (7 is 3 with half its entries negated) and the
