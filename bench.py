@@ -185,7 +185,8 @@ def oracle_fits(name):
 
 def ttmc_kernel_name(w):
     if len(w.dims) == 3 and max(w.ranks) <= 16:
-        return {"f64": "k_ttmc3_mfma<double,double>", "f32": "k_ttmc3_lds<float>", "bf16": "k_ttmc3_lds<bf16>"}[w.dtype]
+        return {"f64": "k_ttmc3_mfma<double,double>", "f32": "k_ttmc3_lds<float, false>",
+                "bf16": "k_ttmc3_lds<bf16, false>"}[w.dtype]
     if len(w.dims) >= 4:
         return "k_ttmc_fiber"
     return "k_ttmc_generic"
@@ -456,7 +457,7 @@ def main():
         print(summarize_trace(args.summarize_trace))
         return
     if args.summarize_pmc:
-        print(summarize_pmc(*args.summarize_pmc, kernel="k_ttmc3_lds<float>"))
+        print(summarize_pmc(*args.summarize_pmc, kernel="k_ttmc3_lds<float, false>"))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the TTMc would "

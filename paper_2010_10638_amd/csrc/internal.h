@@ -118,7 +118,7 @@ struct MemoWs {
     int Ks = 0;                      // inner columns: prod_{k < N-2} R_k
     int nsplit = 1;                  // waves per row of mode N-1
     int32_t* pid_base = nullptr;     // [nchunks of mode N-2] first piece of each chunk
-    int32_t* pj = nullptr;           // [npieces] i_{N-2} of each piece
+    int32_t* pj = nullptr;           // [npieces] i_{N-2} of each piece, in perm order
     int32_t* perm = nullptr;         // [npieces] pieces ordered by i_{N-1} (stream order within)
     int32_t* rptr = nullptr;         // [I_{N-1} + 1] first position of each i_{N-1} in perm
     void* T = nullptr;               // [npieces][Ks] inner sums, TTMc arithmetic type

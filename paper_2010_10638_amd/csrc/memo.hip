@@ -85,6 +85,13 @@ __global__ void k_chunk_base(const int32_t* __restrict__ chunk_ptr, const int32_
     if (c < nchunks) base[c] = (chunk_ptr[c] < P) ? pid[chunk_ptr[c]] : 0;   // an empty chunk writes nothing
 }
 
+// pjs[k] = pj[perm[k]]: the i_{N-2} of the pieces in sorted order (one dependent load fewer)
+__global__ void k_permute_pj(const int32_t* __restrict__ pj, const int32_t* __restrict__ perm, int64_t n,
+                             int32_t* __restrict__ pjs) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) pjs[k] = pj[perm[k]];
+}
+
 // rptr[i] = first position of key i in the sorted keys (i = 0..I)
 __global__ void k_key_ptr(const int32_t* __restrict__ sorted, int64_t n, int64_t I, int32_t* __restrict__ rptr) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -101,7 +108,7 @@ __global__ void k_key_ptr(const int32_t* __restrict__ sorted, int64_t n, int64_t
 struct MemoRowArgs {
     const int32_t* perm;
     const int32_t* rptr;
-    const int32_t* pj;
+    const int32_t* pj;   // i_{N-2} of the pieces in perm order
     const void* T;       // [pieces][Ks], arithmetic type
     const void* U;       // U_{N-2} copy, I x ld, storage type
     int32_t ld, R, Ks, nsplit;
@@ -142,7 +149,7 @@ __global__ __launch_bounds__(64) void k_memo_rows(MemoRowArgs a) {
 #pragma unroll
         for (int g = 0; g < kMemoGroup; ++g) {
             const bool live = k0 + g < hi;
-            const ST* urow = U + (int64_t)a.pj[p[g]] * a.ld;
+            const ST* urow = U + (int64_t)a.pj[min(k0 + g, hi - 1)] * a.ld;
 #pragma unroll
             for (int r = 0; r < RF; ++r) u[g][r] = (live && r < a.R) ? to_at<AT, ST>(urow, r) : AT(0);
 #pragma unroll
@@ -240,7 +247,7 @@ int memo_build(tk_ctx* ctx, hipStream_t s) {
     for (int k = 0; k < N - 2; ++k) Ks *= ctx->ranks[k];
     const size_t at = ytype_size(ctx->dtype);
     const int64_t K = ctx->mode[N - 1].K;
-    const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, (2048 + I - 1) / I));
+    const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, (8192 + I - 1) / I));
     if ((st = dev_alloc((void**)&w.pid_base, (size_t)ml.nchunks * 4)) || (st = dev_alloc((void**)&w.pj, (size_t)np * 4)) ||
         (st = dev_alloc((void**)&w.perm, (size_t)np * 4)) || (st = dev_alloc((void**)&w.rptr, (size_t)(I + 1) * 4)) ||
         (st = dev_alloc(&w.T, (size_t)np * Ks * at)) ||
@@ -268,6 +275,10 @@ int memo_build(tk_ctx* ctx, hipStream_t s) {
                                               (int32_t*)iota.p, w.perm, (int)np, 0, bits, s));
     k_key_ptr<<<cdiv(I + 1, 256), 256, 0, s>>>((const int32_t*)keys_sorted.p, np, I, w.rptr);
     TK_LAUNCH_CHECK("k_key_ptr");
+    // the pieces' i_{N-2} in sorted order, over the unsorted table (no longer needed)
+    k_permute_pj<<<cdiv(np, 256), 256, 0, s>>>(w.pj, w.perm, np, (int32_t*)key.p);
+    TK_LAUNCH_CHECK("k_permute_pj");
+    TK_HIP(hipMemcpyAsync(w.pj, key.p, (size_t)np * 4, hipMemcpyDeviceToDevice, s));
     TK_HIP(hipStreamSynchronize(s));   // the temporaries are freed on return
     w.npieces = np;
     w.Ks = (int)Ks;

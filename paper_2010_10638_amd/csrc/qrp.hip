@@ -1062,8 +1062,8 @@ template <typename YT, typename LT>
 int launch_house_grid(const tk_ctx* ctx, const QrpPlan& p, const YT* src, double* W, int32_t* perm, double* U,
                       LT* Ulp, int ldlp, int32_t* piv, double* gaps, const int32_t* flag, hipStream_t s) {
     auto kern = k_house_qrp_grid<YT, LT>;
-    int occ = 0;
-    TK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, kHouseGridT, 0));
+    static int occ = 0;   // blocks per CU of this kernel (a property of the code object): asked once
+    if (occ == 0) TK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, kHouseGridT, 0));
     const int64_t want = std::min<int64_t>({(int64_t)kHouseGridMaxB, (int64_t)std::max(ctx->ncu, 1) * std::max(occ, 1),
                                             (p.m + TK_HOUSE_ROWS - 1) / TK_HOUSE_ROWS});
     const int nb = (int)std::max<int64_t>(1, want);
