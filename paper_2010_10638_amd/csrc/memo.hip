@@ -150,8 +150,14 @@ __global__ __launch_bounds__(64) void k_memo_rows(MemoRowArgs a) {
         for (int g = 0; g < kMemoGroup; ++g) {
             const bool live = k0 + g < hi;
             const ST* urow = U + (int64_t)a.pj[min(k0 + g, hi - 1)] * a.ld;
+            // the factor copy's rows are ld >= RF values, 16-byte aligned: read them whole
+            // (columns past R are zero in the copy)
+            constexpr int NV = RF * (int)sizeof(ST) / 16;
+            ST raw[RF];
 #pragma unroll
-            for (int r = 0; r < RF; ++r) u[g][r] = (live && r < a.R) ? to_at<AT, ST>(urow, r) : AT(0);
+            for (int v = 0; v < NV; ++v) ((uint4*)raw)[v] = ((const uint4*)urow)[v];
+#pragma unroll
+            for (int r = 0; r < RF; ++r) u[g][r] = live ? to_at<AT, ST>(raw, r) : AT(0);
 #pragma unroll
             for (int j = 0; j < KSL; ++j) {
                 const int cs = lane + 64 * j;

@@ -694,18 +694,20 @@ __global__ __launch_bounds__(1024) void k_house_qrp(const YT* __restrict__ src, 
 
 // The same Householder QRP spread over the whole grid (cooperative launch, grid barriers between
 // phases), for matrices too large for one workgroup to stream quickly.  Block b owns rows
-// [b slab, (b+1) slab).  Per step j:
+// [b slab, (b+1) slab).  Per step j, two barriers:
 //   1. each block: partial squared norms of columns j..n-1 over its rows >= j;      barrier
-//   2. the column totals, each block a share of the columns (fixed addition order);  barrier
-//   3. block 0: first maximum, runner-up, the swap in perm; the pivot, its squared norm and
-//      x0 = A[j][p] (read before any swap) to ctl;                                      barrier
-//   4. each block: swap columns j and p in its rows, v = its part of x + sgn(x0) alpha e_j, with
+//   2. every block alike: the column totals (blocks added in order), first maximum and runner-up,
+//      x0 = A[j][p] from a copy of row j that its owner made before the step; block 0 records the
+//      swap in perm and the gap;
+//   3. each block: swap columns j and p in its rows, v = its part of x + sgn(x0) alpha e_j, with
 //      ||v||^2 = 2 alpha^2 + 2 |x0| alpha; partial v^T A over columns j..n-1;          barrier
-//   5. w = beta v^T A, totals spread as in 2;                                           barrier
-//   6. each block: A -= v w^T on its rows.
-// Q = H_0 ... H_{R-1} [I; 0] the same way (partials, totals, update), then the copies.
-// Every block takes every barrier (all loop bounds and branch conditions are read from the same
-// reduced values), and with a flag the whole grid returns at once when it is clear.
+//   4. every block alike: w = beta v^T A (totals as in 2), then A -= v w^T on its rows; the owner
+//      of row j + 1 copies it.
+// The two partial sets use separate buffers (a block can be writing one while another still reads
+// the other).  Q = H_0 ... H_{R-1} [I; 0] in compact WY form after one more barrier, then the
+// copies.  Every block takes every barrier (all loop bounds and branch conditions come from the
+// same totals, added in the same order on each block), and with a flag the whole grid returns at
+// once when it is clear.
 namespace cg = cooperative_groups;
 
 template <typename YT, typename LT>
@@ -715,7 +717,6 @@ struct HouseGridArgs {
     int64_t m;
     int n, R;
     double* V;                  // m x R reflectors
-    double* w;                  // max(n, R)
     double* beta_s;             // R
     int32_t* perm;              // n
     double* U;                  // m x R
@@ -724,53 +725,45 @@ struct HouseGridArgs {
     int32_t* piv_out;           // R, or null
     double* gaps;               // R, or null
     const int32_t* flag;        // run only when *flag != 0, or null (always run)
-    double* part;               // gridDim.x x max(n, R^2) partials
+    double* part;               // 2 x gridDim.x x max(n, R^2) partials (norms, v^T A)
     double* ctl;                // n: a copy of the row of A at the current step
     int64_t slab;               // rows per block
 };
 
-constexpr int kHouseGridT = 256;
+constexpr int kHouseGridT = 1024;
 
-// out[c] for c in [c0, n): sum over the block's rows i in [lo, hi) of f(i, c); lane = column,
-// wave = row stride; the waves' partials added in order through LDS
+// out[c] for c in [c0, n): sum over the block's rows i in [lo, hi) of f(i, c).  The columns are
+// taken W = min(1024, n - c0 rounded up to 64) at a time, thread t on column t % W and row slice
+// t / W; each thread keeps four partial sums (rows taken in turn) so that four loads are in flight,
+// added as (s0 + s1) + (s2 + s3); the slices are added in order through LDS.
 template <typename F>
 __device__ inline void slab_column_sums(int64_t lo, int64_t hi, int c0, int n, double* red, double* out, F f) {
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    constexpr int NW = kHouseGridT / 64;
-    for (int cb = c0; cb < n; cb += 64) {
-        const int c = cb + lane;
-        double acc = 0.0;
-        if (c < n)
-            for (int64_t i = lo + wv; i < hi; i += NW) acc += f(i, c);
-        red[wv * 64 + lane] = acc;
-        __syncthreads();
-        if (tid < 64 && c < n) {
-            double t = 0.0;
-#pragma unroll
-            for (int k = 0; k < NW; ++k) t += red[k * 64 + lane];
-            out[c] = t;
-        }
-        __syncthreads();
-    }
-}
-
-// out[c] = scale * sum_{k < nb} part[k][c] for the columns c = c0 + b, c0 + b + nb, ... < n of
-// block b: thread t adds the partials k = t, t + 256, ... in order, then the threads' sums are
-// added in a fixed tree (wave shuffles, then the waves in order)
-__device__ inline void grid_column_totals(const double* part, int pw, int nb, int c0, int n, double scale,
-                                          double* red, double* out) {
     const int tid = threadIdx.x;
-    for (int c = c0 + (int)blockIdx.x; c < n; c += nb) {
-        double t = 0.0;
-        for (int k = tid; k < nb; k += kHouseGridT) t += part[(int64_t)k * pw + c];
-        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-        if ((tid & 63) == 0) red[tid >> 6] = t;
+    for (int cb = c0; cb < n; cb += kHouseGridT) {
+        const int W = min(kHouseGridT, (n - cb + 63) / 64 * 64);
+        const int S = kHouseGridT / W;          // row slices (threads past S * W idle)
+        const int col = tid % W, sl = tid / W;
+        const int c = cb + col;
+        double acc = 0.0;
+        if (sl < S && c < n) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int64_t i = lo + sl;
+            const int64_t st = S;
+            for (; i + 3 * st < hi; i += 4 * st) {
+                s0 += f(i, c);
+                s1 += f(i + st, c);
+                s2 += f(i + 2 * st, c);
+                s3 += f(i + 3 * st, c);
+            }
+            for (; i < hi; i += st) s0 += f(i, c);
+            acc = (s0 + s1) + (s2 + s3);
+        }
+        red[tid] = acc;
         __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < kHouseGridT / 64; ++k) s += red[k];
-            out[c] = scale * s;
+        if (sl == 0 && c < n) {
+            double t = 0.0;
+            for (int k = 0; k < S; ++k) t += red[k * W + col];
+            out[c] = t;
         }
         __syncthreads();
     }
@@ -785,12 +778,13 @@ __global__ __launch_bounds__(kHouseGridT) void k_house_qrp_grid(HouseGridArgs<YT
     __shared__ int bp_s[kHouseGridT / 64];
     __shared__ double s_piv[3];             // pivot, its squared norm, x0
     __shared__ double s_T[kGramMaxR][kGramMaxR], s_M[kGramMaxR][kGramMaxR], s_G[kGramMaxR * kGramMaxR];
+    extern __shared__ double tot[];   // this block's copy of the column totals (n values)
     const int tid = threadIdx.x, nb = gridDim.x, b = blockIdx.x;
     const int n = a.n, R = a.R;
     const int64_t m = a.m;
     const int64_t r0 = min(m, (int64_t)b * a.slab), r1 = min(m, r0 + a.slab);
     const int pw = max(n, R * R);
-    double* mypart = a.part + (int64_t)b * pw;
+    double* mypart = a.part + (int64_t)b * pw;   // the Gram of V (after the steps)
     double* rowbuf = a.ctl;                 // row j of A as it stands before step j (n values)
     if (a.src)
         for (int64_t e = r0 * n + tid; e < r1 * n; e += kHouseGridT) a.A[e] = yld(a.src, e);
@@ -799,23 +793,33 @@ __global__ __launch_bounds__(kHouseGridT) void k_house_qrp_grid(HouseGridArgs<YT
     __syncthreads();
     if (r0 <= 0 && 0 < r1)
         for (int c = tid; c < n; c += kHouseGridT) rowbuf[c] = a.A[c];
+    // column totals of a partials buffer, computed by every block alike (fixed order): thread t
+    // takes columns c0 + t, c0 + t + 256, ...
+    auto all_totals = [&](const double* part, int c0, double scale) __attribute__((always_inline)) {
+        for (int c = c0 + tid; c < n; c += kHouseGridT) {
+            double t = 0.0;
+            for (int k = 0; k < nb; ++k) t += part[(int64_t)k * pw + c];
+            tot[c] = scale * t;
+        }
+        __syncthreads();
+    };
+    double* const partA = a.part;                       // column norms
+    double* const partB = a.part + (int64_t)nb * pw;    // v^T A
     for (int j = 0; j < R; ++j) {
-        // 1. partial squared norms
-        slab_column_sums(max(r0, (int64_t)j), r1, j, n, red, mypart, [&](int64_t i, int c) {
+        // 1. partial squared norms (this block's rows >= j)
+        slab_column_sums(max(r0, (int64_t)j), r1, j, n, red, partA + (int64_t)b * pw, [&](int64_t i, int c) {
             const double x = a.A[i * n + c];
             return x * x;
         });
         grid.sync();
-        // 2. column totals, spread over the blocks
-        grid_column_totals(a.part, pw, nb, j, n, 1.0, red, a.w);
-        grid.sync();
-        // 3. every block: pivot (first maximum) and runner-up over the totals, the same result on
+        // 2. every block: the column totals, the pivot (first maximum) and runner-up, the same on
         // each; x0 from the copy of row j
+        all_totals(partA, j, 1.0);
         {
             double bv = -1.0, b2 = -1.0;
             int bp = n;
             for (int c = j + tid; c < n; c += kHouseGridT) {   // ascending: first maximum kept
-                const double t = a.w[c];
+                const double t = tot[c];
                 if (t > bv) { b2 = fmax(b2, bv); bv = t; bp = c; }
                 else b2 = fmax(b2, t);
             }
@@ -847,7 +851,7 @@ __global__ __launch_bounds__(kHouseGridT) void k_house_qrp_grid(HouseGridArgs<YT
             }
             __syncthreads();
         }
-        // 4. swap, reflector, partial v^T A
+        // 3. swap, reflector, partial v^T A
         const int p = (int)s_piv[0];
         const double alpha = sqrt(s_piv[1]), x0 = s_piv[2];
         if (p != j)
@@ -876,16 +880,15 @@ __global__ __launch_bounds__(kHouseGridT) void k_house_qrp_grid(HouseGridArgs<YT
         const double beta = 2.0 / (2.0 * alpha * alpha + 2.0 * fabs(x0) * alpha);
         if (b == 0 && tid == 0) a.beta_s[j] = beta;
         __syncthreads();
-        slab_column_sums(max(r0, (int64_t)j), r1, j, n, red, mypart,
+        slab_column_sums(max(r0, (int64_t)j), r1, j, n, red, partB + (int64_t)b * pw,
                          [&](int64_t i, int c) { return a.V[i * R + j] * a.A[i * n + c]; });
         grid.sync();
-        // 5. w = beta v^T A, spread over the blocks
-        grid_column_totals(a.part, pw, nb, j, n, beta, red, a.w);
-        grid.sync();
-        // 6. A -= v w^T on this block's rows >= j; the owner of row j + 1 copies it for step j + 1
+        // 4. every block: w = beta v^T A, then A -= v w^T on its rows >= j; the owner of row j + 1
+        // copies it for step j + 1
+        all_totals(partB, j, beta);
         for (int64_t i = max(r0, (int64_t)j); i < r1; ++i) {
             const double vi = a.V[i * R + j];
-            for (int c = j + tid; c < n; c += kHouseGridT) a.A[i * n + c] -= vi * a.w[c];
+            for (int c = j + tid; c < n; c += kHouseGridT) a.A[i * n + c] -= vi * tot[c];
         }
         __syncthreads();   // the next step's column sums read these rows from other threads
         if (r0 <= j + 1 && j + 1 < r1)
@@ -998,7 +1001,7 @@ struct QrpPlan {
 // Householder inputs of at least this many entries take the grid-wide kernel, with at least
 // TK_HOUSE_ROWS rows per block
 constexpr int64_t kHouseGridMin = 1 << 18;
-constexpr int kHouseGridMaxB = 256;
+constexpr int kHouseGridMaxB = 64;
 #ifndef TK_HOUSE_ROWS
 #define TK_HOUSE_ROWS 32
 #endif
@@ -1050,7 +1053,7 @@ QrpPlan plan(const tk_ctx* ctx, int mode) {
     p.o_beta = off; off += R;
     p.grid = hm * hn >= kHouseGridMin && R <= kGramMaxR;
     if (p.grid) {
-        p.o_hpart = off; off += (int64_t)kHouseGridMaxB * std::max<int64_t>(hn, (int64_t)R * R);
+        p.o_hpart = off; off += 2 * (int64_t)kHouseGridMaxB * std::max<int64_t>(hn, (int64_t)R * R);
         p.o_hctl = off; off += hn;
     }
     p.total = off;
@@ -1062,8 +1065,11 @@ template <typename YT, typename LT>
 int launch_house_grid(const tk_ctx* ctx, const QrpPlan& p, const YT* src, double* W, int32_t* perm, double* U,
                       LT* Ulp, int ldlp, int32_t* piv, double* gaps, const int32_t* flag, hipStream_t s) {
     auto kern = k_house_qrp_grid<YT, LT>;
-    static int occ = 0;   // blocks per CU of this kernel (a property of the code object): asked once
-    if (occ == 0) TK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, kHouseGridT, 0));
+    const size_t shmem = (size_t)p.n * sizeof(double);   // the block's column totals
+    static int occ = 0;   // blocks per CU at the largest totals array: asked once
+    if (occ == 0)
+        TK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, kHouseGridT,
+                                                            (size_t)TK_MAX_KCOLS * sizeof(double)));
     const int64_t want = std::min<int64_t>({(int64_t)kHouseGridMaxB, (int64_t)std::max(ctx->ncu, 1) * std::max(occ, 1),
                                             (p.m + TK_HOUSE_ROWS - 1) / TK_HOUSE_ROWS});
     const int nb = (int)std::max<int64_t>(1, want);
@@ -1074,7 +1080,6 @@ int launch_house_grid(const tk_ctx* ctx, const QrpPlan& p, const YT* src, double
     a.n = p.n;
     a.R = p.R;
     a.V = W + p.o_V;
-    a.w = W + p.o_w;
     a.beta_s = W + p.o_beta;
     a.perm = perm;
     a.U = U;
@@ -1087,7 +1092,7 @@ int launch_house_grid(const tk_ctx* ctx, const QrpPlan& p, const YT* src, double
     a.ctl = W + p.o_hctl;
     a.slab = (p.m + nb - 1) / nb;
     void* args[] = {&a};
-    TK_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)nb), dim3(kHouseGridT), args, 0, s));
+    TK_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)nb), dim3(kHouseGridT), args, shmem, s));
     return TK_OK;
 }
 
