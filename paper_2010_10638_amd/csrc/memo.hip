@@ -226,6 +226,7 @@ bool memo_applicable(const tk_ctx* ctx) {
 int memo_build(tk_ctx* ctx, hipStream_t s) {
     MemoWs& w = ctx->memo;
     if (w.state != 0) return TK_OK;
+    free_memo(ctx);   // what an earlier attempt that failed part-way left
     if (!memo_applicable(ctx)) {
         w.state = -1;
         return TK_OK;
