@@ -72,6 +72,117 @@ __global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, 
         }
 }
 
+// Partial C over one slab of rows for Y of at most 128 columns (one or two 64-column blocks, up
+// to three block pairs).  Rows come in chunks of 32, staged through LDS in Y's precision (the next
+// chunk's loads in flight during the current one); wave w takes the 4-row steps 2w and 2w+1 of
+// each chunk and accumulates all 16 16x16 tiles of the pair for them, so that per step a lane
+// reads 4 + 4 operands for up to 16 v_mfma_f64_16x16x4f64 (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] and holds D[l/16 + 4v][l%16] in result v).  Tiles that start at or past column n
+// are skipped, and so are the lower tiles (ti > tj) of a diagonal pair, which reads its one panel
+// once and writes the lower tiles as the mirror of the upper ones: on 100 columns 28 tile MFMAs
+// per step instead of 48.  At the end the four waves' sums are added through LDS in wave order.
+// blockIdx.x enumerates the upper block pairs, blockIdx.y the row slab; part[split] receives the
+// n x n partial (entries of upper block pairs only).
+template <typename YT>
+__global__ __launch_bounds__(256, 2) void k_gram_rows(const YT* __restrict__ Y, int64_t m, int n,
+                                                      int nb, int64_t slab, double* __restrict__ part) {
+    constexpr int kStage = 2 * 32 * 65 * (int)sizeof(YT);
+    static_assert(2 * kStage >= 64 * 64 * (int)sizeof(double), "the reduction reuses the staging LDS");
+    __shared__ __align__(16) char lds[2 * kStage];
+    YT(*As)[32][65] = (YT(*)[32][65])lds;
+    YT(*Bs)[32][65] = (YT(*)[32][65])(lds + kStage);
+    int b = blockIdx.x, bi = 0;
+    while (b >= nb - bi) { b -= nb - bi; ++bi; }
+    const int bj = bi + b;
+    const bool diag = bi == bj;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int kq = lane >> 4, c16 = lane & 15;
+    // live tiles: bit 4 ti + tj
+    unsigned live = 0;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+            if (64 * bi + 16 * ti < n && 64 * bj + 16 * tj < n && !(diag && ti > tj)) live |= 1u << (4 * ti + tj);
+    const int64_t r0 = (int64_t)blockIdx.y * slab;
+    const int64_t r1 = min(m, r0 + slab);
+    d4_t acc[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc[t] = d4_t{0, 0, 0, 0};
+    YT xa[8], xb[8];
+    atb_stage(Y, n, n, Y, n, n, r0, r1, bi * 64, bj * 64, xa, xb);
+    int buf = 0;
+    for (int64_t row0 = r0; row0 < r1; row0 += 32) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            const int rr = e >> 6, cc = e & 63;
+            const bool rv = row0 + rr < r1;
+            As[buf][rr][cc] = (rv && bi * 64 + cc < n) ? xa[k] : YT(0);
+            Bs[buf][rr][cc] = (rv && bj * 64 + cc < n) ? xb[k] : YT(0);
+        }
+        __syncthreads();
+        if (row0 + 32 < r1) atb_stage(Y, n, n, Y, n, n, row0 + 32, r1, bi * 64, bj * 64, xa, xb);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int rr = 8 * w + 4 * h + kq;
+            double av[4], bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                av[t] = (double)As[buf][rr][16 * t + c16];
+                bv[t] = (double)Bs[buf][rr][16 * t + c16];
+            }
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj)
+                    if (live & (1u << (4 * ti + tj)))
+                        acc[4 * ti + tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[4 * ti + tj], 0, 0, 0);
+        }
+        buf ^= 1;
+    }
+    // the four waves' sums, added in wave order through LDS: red[tile][v][lane]
+    __syncthreads();
+    double* red = (double*)lds;
+    for (int ww = 0; ww < 4; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (live & (1u << t))
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        double* r = red + (t * 4 + v) * 64 + lane;
+                        *r = (ww == 0) ? acc[t][v] : *r + acc[t][v];
+                    }
+        }
+        __syncthreads();
+    }
+    double* P = part + (int64_t)blockIdx.y * n * n;
+    for (int e = threadIdx.x; e < 16 * 4 * 64; e += 256) {
+        const int t = e >> 8, v = (e >> 6) & 3, l = e & 63;
+        if (!(live & (1u << t))) continue;
+        const int ti = t >> 2, tj = t & 3;
+        const int i = bi * 64 + 16 * ti + (l >> 4) + 4 * v;
+        const int j = bj * 64 + 16 * tj + (l & 15);
+        if (i < n && j < n) {
+            const double x = red[e];
+            P[(int64_t)i * n + j] = x;
+            if (diag && ti < tj) P[(int64_t)j * n + i] = x;
+        }
+    }
+}
+
+// Gram partials of Y (m x n) into part[nsplit][n][n]: the row-split kernel for n <= 128, the
+// tile-row kernel above it
+template <typename YT>
+void launch_gram_partial(const YT* Y, int64_t m, int n, int nb, int nsplit, int64_t slab, double* part,
+                         hipStream_t s) {
+    const dim3 g((unsigned)(nb * (nb + 1) / 2), (unsigned)nsplit);
+    if (nb <= 2) k_gram_rows<YT><<<g, 256, 0, s>>>(Y, m, n, nb, slab, part);
+    else k_gram_partial<YT><<<g, 256, 0, s>>>(Y, m, n, nb, slab, part);
+}
+
 // Sums the partials of entries in upper block pairs (bi <= bj) in split order and writes both
 // C[i][j] and its mirror C[j][i].
 __global__ void k_gram_reduce(const double* __restrict__ part, int nsplit, int n, double* __restrict__ C) {
@@ -1108,8 +1219,7 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
     const int64_t I = ctx->dims[mode];
     const int64_t K = ctx->mode[mode].K;
     if (p.route == 0) {
-        dim3 g1((unsigned)(p.nb * (p.nb + 1) / 2), (unsigned)p.nsplit);
-        k_gram_partial<YT><<<g1, 256, 0, s>>>(Y, p.m, p.n, p.nb, p.slab, W + p.o_part);
+        launch_gram_partial<YT>(Y, p.m, p.n, p.nb, p.nsplit, p.slab, W + p.o_part, s);
         TK_LAUNCH_CHECK("k_gram_partial");
         k_gram_reduce<<<cdiv((int64_t)p.n * p.n, 256), 256, 0, s>>>(W + p.o_part, p.nsplit, p.n, W + p.o_C);
         TK_LAUNCH_CHECK("k_gram_reduce");
@@ -1184,8 +1294,7 @@ int gram_typed(tk_ctx* ctx, int mode, const YT* Y, double** A, int* n, hipStream
     const QrpPlan p = plan(ctx, mode);
     double* W = ctx->ws.qrp;
     if (p.route == 0) {
-        dim3 g1((unsigned)(p.nb * (p.nb + 1) / 2), (unsigned)p.nsplit);
-        k_gram_partial<YT><<<g1, 256, 0, s>>>(Y, p.m, p.n, p.nb, p.slab, W + p.o_part);
+        launch_gram_partial<YT>(Y, p.m, p.n, p.nb, p.nsplit, p.slab, W + p.o_part, s);
         TK_LAUNCH_CHECK("k_gram_partial");
         k_gram_reduce<<<cdiv((int64_t)p.n * p.n, 256), 256, 0, s>>>(W + p.o_part, p.nsplit, p.n, W + p.o_C);
         TK_LAUNCH_CHECK("k_gram_reduce");

@@ -300,6 +300,10 @@ def qrp_case(tk, dtype, dims, ranks, mode, nnz, seed, fat_rule=True):
     ([4000, 40, 40], [24, 32, 32], 0, 40000), # tall, Gram route, K = 1024, R > 16, L^T in memory
     ([3000, 40, 40], [20, 16, 16], 0, 40000), # tall, Gram route, K = 256, 16 < R <= 32: L in LDS
     ([200, 40, 30], [8, 8, 8], 0, 5000),      # small, Gram route
+    ([3000, 10, 10], [10, 10, 10], 0, 30000), # Gram route, K = 100: two column blocks, ragged tile
+    ([2003, 16, 8], [6, 16, 8], 0, 20000),    # Gram route, K = 128, ragged last row chunk
+    ([2500, 8, 9], [9, 8, 9], 0, 20000),      # Gram route, K = 72: second block one live tile
+    ([1000, 3, 3], [4, 3, 3], 0, 3000),       # Gram route, K = 9: one partly live tile
     ([400, 40, 40], [34, 6, 6], 0, 8000),     # R > 32: Householder route
     ([1500, 60, 50], [8, 40, 30], 0, 30000),  # K = 1200 > 1024: Householder route
     ([20, 30, 25, 40], [5, 4, 4, 4], 0, 6000),  # fat (K = 64 > 20): Householder on Y Y^T
