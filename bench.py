@@ -186,7 +186,7 @@ def oracle_fits(name):
 def ttmc_kernel_name(w):
     if len(w.dims) == 3 and max(w.ranks) <= 16:
         return {"f64": "k_ttmc3_mfma<double,double>", "f32": "k_ttmc3_lds<float, false>",
-                "bf16": "k_ttmc3_lds<bf16, false>"}[w.dtype]
+                "bf16": "k_ttmc3_bf"}[w.dtype]
     if len(w.dims) >= 4:
         return "k_ttmc_fiber"
     return "k_ttmc_generic"

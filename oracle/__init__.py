@@ -9,7 +9,11 @@ numpy arrays into it, plus three definitions that are a library primitive applie
 
 * :func:`coalesce` and :func:`csf` - the mode-sorted layout, defined by a stable lexicographic
   sort (``numpy.lexsort``) of the coordinate tuples;
-* :func:`svd_factor` - the SVD factor update of standard HOOI (paper Alg. 1), via LAPACK.
+* :func:`svd_factor` - the SVD factor update of standard HOOI (paper Alg. 1), via LAPACK;
+
+and, in numpy, the order-3 TTMc with BF16 matrix-core operands (:func:`ttmc_bf16_operands`:
+each product x a rounded once to BF16, then one matrix product per row) and the BF16 rounding
+it uses (:func:`bf16_nearest`, written from the definition of round to nearest, ties to even).
 
 Pins (tests/test_oracle_pins.py) tie every function here to something other than itself.  The
 completion loss/gradient is pinned by central finite differences and by the zero-residual case.
@@ -102,6 +106,43 @@ def ttmc(coords, vals, dims, ranks, mode: int, U, threads: int = 1) -> np.ndarra
         st = _load().orc_ttmc(dims.size, _p(dims), _p(ranks), vals.size, _p(coords), _p(vals), mode,
                               _ptr_array(U), _p(Y))
     _check(st, "ttmc")
+    return Y
+
+
+def bf16_nearest(x) -> np.ndarray:
+    """Nearest BF16 number to each FP64 value (8 significant bits, halves to even), as FP64.
+
+    From the definition: with x = m 2^e, 0.5 <= |m| < 1 (frexp), the BF16 numbers near x are the
+    multiples of 2^(e-8); x / 2^(e-8) is exact and numpy.round takes halves to the even integer.
+    For finite inputs of normal BF16 magnitude (no overflow or subnormal handling)."""
+    x = np.asarray(x, dtype=np.float64)
+    _, e = np.frexp(x)
+    q = np.ldexp(1.0, e - 8)
+    return np.where(x == 0, 0.0, np.round(x / q) * q)
+
+
+def ttmc_bf16_operands(coords, vals, dims, ranks, mode: int, U) -> np.ndarray:
+    """Order-3 TTMc with BF16 matrix-core operands: Y_(n)(i_n, :) = sum_p bf16(x_p a_p) kron b_p,
+    where a_p and b_p are the rows U_s(i_s, :) and U_t(i_t, :) of the two other modes s < t, the
+    product x_p a_p is formed exactly and rounded once to the nearest BF16 number (the reading
+    the BF16 form of the Alg. 2 TTMc takes on matrix cores), and everything else is FP64.  Values
+    and factors are taken as given (callers pass them already rounded to BF16).  Plain numpy: one
+    (R_s x nnz_row) @ (nnz_row x R_t) product per row, flattened with t fastest."""
+    coords = np.asarray(coords)
+    vals = np.asarray(vals, dtype=np.float64)
+    if coords.shape[0] != 3:
+        raise ValueError("the BF16-operand TTMc is the order-3 form")
+    s, t = [k for k in range(3) if k != mode]
+    A = np.asarray(U[s], dtype=np.float64)[coords[s]]
+    B = np.asarray(U[t], dtype=np.float64)[coords[t]]
+    P = bf16_nearest(vals[:, None] * A)
+    Y = np.zeros((int(dims[mode]), int(ranks[s]) * int(ranks[t])))
+    order = np.argsort(coords[mode], kind="stable")
+    rows = coords[mode][order]
+    cut = np.flatnonzero(np.diff(rows)) + 1
+    for seg in np.split(order, cut):
+        if seg.size:
+            Y[coords[mode][seg[0]]] = (P[seg].T @ B[seg]).ravel()
     return Y
 
 

@@ -13,6 +13,10 @@
 //   k_ttmc3_mfma  - order 3 with R_a, R_b <= 16.  The row sum  sum_p (x_p a_p) b_p^T  is a
 //                   rank-k product over the row's nonzeros, computed 4 nonzeros at a time by
 //                   v_mfma_{f32,f64}_16x16x4: lane l carries nonzero l/16 and factor column l%16.
+//   k_ttmc3_lds   - the same for FP32 storage with the batch's factor rows staged in LDS tiles
+//                   (and, in its residual form, the completion residuals formed inside).
+//   k_ttmc3_bf    - the same for BF16 storage on v_mfma_f32_16x16x32_bf16, 32 nonzeros per
+//                   instruction, the tiles column-major and x_p a_p rounded once to BF16.
 //   k_ttmc_generic- any order 2..8 and K_n <= 4096 on the vector ALU; lane l owns columns l+64j.
 #include "internal.h"
 
@@ -246,7 +250,8 @@ __global__ __launch_bounds__(256) void k_ttmc3_mfma(TtmcArgs a) {
     }
 }
 
-// Order-3 TTMc (R_a, R_b <= 16) on FP32 MFMA for FP32 or BF16 storage, walking the padded stream
+// Order-3 TTMc (R_a, R_b <= 16) on FP32 MFMA (the library runs it on FP32 storage; BF16 storage
+// takes k_ttmc3_bf below, whose batch pipeline is the same), walking the padded stream
 // of a chunk in batches of 64 entries regardless of row boundaries (rows are padded to whole
 // 4-entry steps).  Software pipeline per wave, iteration b:
 //   1. read batch b's factor rows (from the wave's LDS tile) and values into registers;
@@ -589,6 +594,200 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a, ResArgs res) {
 #undef TK_P1
 #undef TK_GATHER
 #undef TK_PUT
+}
+
+// Order-3 TTMc with BF16 operands on the BF16 matrix instruction (v_mfma_f32_16x16x32_bf16, 32
+// nonzeros per instruction).  That instruction takes, in lane l, eight consecutive values of the
+// contraction index (nonzeros 8(l/16)..+7) for one factor column l%16, so the wave's tile is kept
+// column-major: At[c][e] = bf16(x_e * a_e[c]) (the product of two BF16 numbers, exact in FP32, is
+// rounded once to BF16 as the tile is written) and Bt[c][e] = b_e[c].  The batch pipeline is that of
+// the FP32-tile kernel above (stream two batches ahead, rows gathered one batch ahead with 16-byte
+// loads, two lanes per 32-byte row); the gathered rows are transposed into the tile with 2-byte
+// LDS writes.  A batch that lies inside one row takes two MFMAs; a batch in which rows open takes
+// the 16 FP32 steps of four nonzeros each (v_mfma_f32_16x16x4f32 on the same tile values), writing
+// each finished row out before the step that opens the next.  Either way every product is
+// bf16(x a) * b, exact in FP32, and the sums are FP32.
+constexpr int kBfStride = 72;   // entries per tile column: 144-byte rows keep the 16-byte reads of
+                                // 16 columns on distinct banks
+
+struct BfTiles {
+    bf16_t At[16][kBfStride];
+    bf16_t Bt[16][kBfStride];
+    float x[64];
+    int32_t ia[64];
+    int32_t ib[64];
+};
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void k_ttmc3_bf(TtmcArgs a) {
+    constexpr int ROWB = 32;   // bytes of one padded BF16 factor row
+    __shared__ __align__(16) BfTiles tiles[4];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const int ch = blockIdx.x * 4 + w;
+    if (ch >= a.nchunks) return;
+    BfTiles& T = tiles[w];
+    const int kq = lane >> 4, m = lane & 15;
+    const int q0 = a.chunk_ptr[ch], q1 = a.chunk_ptr[ch + 1];
+    const int slot = a.chunk_slot[ch];
+    const int32_t* __restrict__ ia = a.idx;
+    const int32_t* __restrict__ ib = a.idx + a.nnz;
+    const char* __restrict__ Fa = (const char*)a.F[0];
+    const char* __restrict__ Fb = (const char*)a.F[1];
+    const int Ra = a.R[0], Rb = a.R[1], K = a.K;
+    const int s0 = a.chunk_row[ch];
+    int s = s0;
+    f4_t acc = {0, 0, 0, 0};
+
+    // rows of the chunk: as in the FP32-tile kernel
+    int rbase = s0;
+    int rowsv = ld_const(a.rows, min(s0 + lane, a.S - 1));
+    int prev_id = (s0 > 0) ? ld_const(a.rows, s0 - 1) : -1;
+    auto flush = [&](int row) __attribute__((always_inline)) {
+        const bool owner = (row != s0) || (slot < 0);
+        const int id = __builtin_amdgcn_readlane(rowsv, row - rbase);
+        const uint64_t base = owner ? (uint64_t)(uintptr_t)a.Y : (uint64_t)(uintptr_t)a.carry;
+        const int64_t off = owner ? (int64_t)id * K : (int64_t)slot * K;
+        float* dst = (float*)(uintptr_t)base + off;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 4 * kq + v;
+            if (r < Ra && m < Rb) dst[r * Rb + m] = acc[v];
+        }
+        if (owner && (id != prev_id + 1 || row == a.S - 1)) zero_gaps_ids<float>(a, row, prev_id, id, lane);
+        prev_id = id;
+    };
+    // stream loads at a clamped position, with no branch around them and the raw BF16 value kept:
+    // entries past the chunk end are masked (index 0, value 0) only when the batch is staged, so
+    // no wait for the stream holds up the gathers in flight
+    auto stream_load = [&](int pstart, int& ra, int& rb, int& rx) __attribute__((always_inline)) {
+        const int qc = max(min(pstart + lane, q1 - 1), 0);
+        ra = ia[qc];
+        rb = ib[qc];
+        rx = ((const bf16_t*)a.val)[qc];
+    };
+    auto stage = [&](int ra, int rb, int rx, int pstart) __attribute__((always_inline)) -> uint64_t {
+        const bool v = pstart + lane < q1;
+        ra = v ? ra : 0;
+        rb = v ? rb : 0;
+        const uint64_t st = __ballot(ra < 0);
+        T.ia[lane] = ra & kIndexMask;
+        T.ib[lane] = rb;
+        T.x[lane] = v ? bf16_to_f32((bf16_t)rx) : 0.f;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        return st;
+    };
+    // gather instruction j: lane l loads 16 bytes (columns 8(l%2)..+7) of entry 32 j + l/2
+    uint4 ga0, ga1, gb0, gb1;
+    auto gather = [&]() __attribute__((always_inline)) {
+        const uint32_t part = (uint32_t)(lane & 1) * 16u;
+        const int r0 = lane >> 1, r1 = 32 + (lane >> 1);
+        ga0 = *(const uint4*)(Fa + ((uint32_t)T.ia[r0] * (uint32_t)ROWB + part));
+        gb0 = *(const uint4*)(Fb + ((uint32_t)T.ib[r0] * (uint32_t)ROWB + part));
+        ga1 = *(const uint4*)(Fa + ((uint32_t)T.ia[r1] * (uint32_t)ROWB + part));
+        gb1 = *(const uint4*)(Fb + ((uint32_t)T.ib[r1] * (uint32_t)ROWB + part));
+    };
+    // transpose the gathered rows into the tile, a scaled by the entry's value
+    auto put_one = [&](const uint4& ua, const uint4& ub, int e) __attribute__((always_inline)) {
+        const float xe = T.x[e];
+        const int c0 = 8 * (lane & 1);
+        const uint32_t wa[4] = {ua.x, ua.y, ua.z, ua.w};
+        const uint32_t wb[4] = {ub.x, ub.y, ub.z, ub.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float lo = __uint_as_float(wa[i] << 16) * xe;
+            const float hi = __uint_as_float(wa[i] & 0xffff0000u) * xe;
+            const bf16x2_t p = __builtin_convertvector((float __attribute__((ext_vector_type(2)))){lo, hi}, bf16x2_t);
+            const uint32_t pk = __builtin_bit_cast(uint32_t, p);
+            T.At[c0 + 2 * i][e] = (bf16_t)(pk & 0xffffu);
+            T.At[c0 + 2 * i + 1][e] = (bf16_t)(pk >> 16);
+            T.Bt[c0 + 2 * i][e] = (bf16_t)(wb[i] & 0xffffu);
+            T.Bt[c0 + 2 * i + 1][e] = (bf16_t)(wb[i] >> 16);
+        }
+    };
+    auto put = [&]() __attribute__((always_inline)) {
+        put_one(ga0, gb0, lane >> 1);
+        put_one(ga1, gb1, 32 + (lane >> 1));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+
+    // prologue: batch 0 staged and its rows in the tile; stream registers for batches 1 and 2
+    int r1a, r1b, r2a, r2b, r1x, r2x;
+    uint64_t starts;
+    {
+        int r0a, r0b, r0x;
+        stream_load(q0, r0a, r0b, r0x);
+        stream_load(q0 + 64, r1a, r1b, r1x);
+        stream_load(q0 + 128, r2a, r2b, r2x);
+        starts = stage(r0a, r0b, r0x, q0);
+        gather();
+        put();
+    }
+    // one batch: ra/rb/rx hold batch b+1 and then receive batch b+3 (the loop below alternates two
+    // register sets, so that no copy waits for a stream load in flight)
+    auto batch = [&](int p, int& ra, int& rb, int& rx) __attribute__((always_inline)) {
+        const int nsteps = min(16, (q1 - p) >> 2);
+        const bool plain = starts == 0 || (starts == 1ull && p == q0);   // no row opens inside
+        // 1. stage batch b+1, gather its rows, then the stream loads of batch b+3
+        const uint64_t starts_next = stage(ra, rb, rx, p + 64);
+        const int s_next = s + __popcll(starts & ~((p == q0) ? 1ull : 0ull));
+        const int rows_next = ld_const(a.rows, min(s_next + lane, a.S - 1));
+        gather();
+        stream_load(p + 192, ra, rb, rx);
+        // 2. batch b from the tile
+        if (plain) {
+            // entries past the chunk end carry zero values
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (32 * j < q1 - p) {
+                    const bf16x8_t av = *(const bf16x8_t*)&T.At[m][32 * j + 8 * kq];
+                    const bf16x8_t bv = *(const bf16x8_t*)&T.Bt[m][32 * j + 8 * kq];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+                }
+            }
+        } else {
+            // rows open inside the batch: step t contracts entries 4t..4t+3 (lane l: entry
+            // 4t + l/16, column l%16); a finished row is written before the step opening the next
+            const uint64_t opens = starts & ~((p == q0) ? 1ull : 0ull);
+#pragma unroll
+            for (int t0 = 0; t0 < 16; t0 += 8) {
+                float av[8], bv[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    av[t] = bf16_to_f32(T.At[m][4 * (t0 + t) + kq]);
+                    bv[t] = bf16_to_f32(T.Bt[m][4 * (t0 + t) + kq]);
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    if (t0 + t < nsteps) {
+                        if ((opens >> (4 * (t0 + t))) & 1ull) {
+                            flush(s);
+                            ++s;
+                            acc = f4_t{0, 0, 0, 0};
+                        }
+                        acc = Acc<float>::mfma(av[t], bv[t], acc);
+                    }
+                }
+            }
+        }
+        // 3. batch b+1's rows into the tile
+        put();
+        starts = starts_next;
+        rbase = s_next;
+        rowsv = rows_next;
+    };
+    for (int p = q0; p < q1; p += 128) {
+        batch(p, r1a, r1b, r1x);
+        if (p + 64 >= q1) break;
+        batch(p + 64, r2a, r2b, r2x);
+    }
+    flush(s);
 }
 
 template <typename AT, typename ST, int KPL>
@@ -1120,8 +1319,8 @@ int ttmc_run(tk_ctx* ctx, int mode, void* Y, hipStream_t s, hipEvent_t* ev_main,
             k_ttmc3_lds<float, false><<<grid, 256, 0, s>>>(a, ResArgs{});
             TK_LAUNCH_CHECK("k_ttmc3_lds");
         } else {
-            k_ttmc3_lds<bf16_t, false><<<grid, 256, 0, s>>>(a, ResArgs{});
-            TK_LAUNCH_CHECK("k_ttmc3_lds");
+            k_ttmc3_bf<<<grid, 256, 0, s>>>(a);
+            TK_LAUNCH_CHECK("k_ttmc3_bf");
         }
     } else if (fiber_ok) {
         // factor copies of 8 columns (every rank <= 8) or 16

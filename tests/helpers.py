@@ -1,4 +1,5 @@
-"""Small test-side helpers (no decomposition arithmetic)."""
+"""Small test-side helpers: input rounding, error norms, and the choice of oracle reference for a
+rounded GPU path (no decomposition arithmetic of their own)."""
 import numpy as np
 
 
@@ -37,3 +38,21 @@ def cast_vals(v, dtype):
     if dtype == "f32":
         return np.asarray(v, dtype=np.float32).astype(np.float64)
     return bf16_value(v)
+
+
+def bf16_matrix_core_path(dims, ranks, mode) -> bool:
+    """Whether a BF16 TTMc of this mode runs on the BF16 matrix instruction: order 3 with both
+    other ranks at most 16 (the library's rule for its order-3 kernel)."""
+    return len(dims) == 3 and all(r <= 16 for t, r in enumerate(ranks) if t != mode)
+
+
+def oracle_ttmc_rounded(coords, vals, dims, ranks, mode, U, dtype):
+    """The oracle's TTMc on the inputs as the GPU path holds them (values and factors rounded to
+    the storage type); on the BF16 matrix-core path also with each product x a rounded to BF16,
+    the one rounding that path adds.  What remains against the GPU is FP32 accumulation order."""
+    import oracle
+    v, Uc = cast_vals(vals, dtype), cast_inputs(U, dtype)
+    if dtype == "bf16" and bf16_matrix_core_path(dims, ranks, mode):
+        return oracle.ttmc_bf16_operands(coords, v, dims, ranks, mode, Uc)
+    return oracle.ttmc(coords, v, dims, ranks, mode, Uc)
+

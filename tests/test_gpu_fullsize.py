@@ -15,7 +15,7 @@ import torch
 
 import oracle
 import synth
-from helpers import cast_inputs, cast_vals, rel_fro
+from helpers import cast_inputs, cast_vals, oracle_ttmc_rounded, rel_fro
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -128,7 +128,7 @@ def rows_by_oracle(w, mode, rows, U, dtype):
     c = w.coords[:, keep]
     v = w.vals[keep]
     Yo = oracle.ttmc(c, v, w.dims, w.ranks, mode, U)[rows]
-    Yc = oracle.ttmc(c, cast_vals(v, dtype), w.dims, w.ranks, mode, cast_inputs(U, dtype))[rows]
+    Yc = oracle_ttmc_rounded(c, v, w.dims, w.ranks, mode, U, dtype)[rows]
     return Yo, Yc
 
 

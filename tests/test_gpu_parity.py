@@ -5,7 +5,7 @@ import torch
 
 import oracle
 import synth
-from helpers import bf16_round, cast_inputs, cast_vals, rel_fro
+from helpers import bf16_round, cast_inputs, cast_vals, oracle_ttmc_rounded, rel_fro
 
 pytestmark = pytest.mark.gpu
 
@@ -141,7 +141,7 @@ def test_ttmc_parity(tk, dtype, case):
         err = rel_fro(Y, Yo)
         assert err <= TOL_Y[dtype], (mode, err)
         # same rounded inputs: only the accumulation differs
-        Yc = oracle.ttmc(w.coords, cast_vals(w.vals, dtype), dims, ranks, mode, cast_inputs(w.U_init, dtype))
+        Yc = oracle_ttmc_rounded(w.coords, w.vals, dims, ranks, mode, w.U_init, dtype)
         assert rel_fro(Y, Yc) <= (1e-13 if dtype == "f64" else 2e-6), (mode, rel_fro(Y, Yc))
 
 
@@ -180,7 +180,7 @@ def test_ttmc_long_rows(tk, dtype):
     Y = Y.double().cpu().numpy()
     Yo = oracle.ttmc(coords, vals, dims, ranks, 0, U)
     assert rel_fro(Y, Yo) <= TOL_Y[dtype]
-    Yc = oracle.ttmc(coords, cast_vals(vals, dtype), dims, ranks, 0, cast_inputs(U, dtype))
+    Yc = oracle_ttmc_rounded(coords, vals, dims, ranks, 0, U, dtype)
     assert rel_fro(Y, Yc) <= 2e-6
     # rows: every non-empty row matches on its own (short rows next to long ones), empty rows are 0
     lens = np.bincount(coords[0], minlength=dims[0])
@@ -233,7 +233,7 @@ def test_ttmc3_skewed_rows_and_fibers(tk, dtype, case):
         Y = Yt.double().cpu().numpy()
         Yo = oracle.ttmc(coords, vals, dims, ranks, mode, U)
         assert rel_fro(Y, Yo) <= TOL_Y[dtype], (mode, rel_fro(Y, Yo))
-        Yc = oracle.ttmc(coords, cast_vals(vals, dtype), dims, ranks, mode, cast_inputs(U, dtype))
+        Yc = oracle_ttmc_rounded(coords, vals, dims, ranks, mode, U, dtype)
         assert rel_fro(Y, Yc) <= 2e-6, (mode, rel_fro(Y, Yc))
         lens = np.bincount(coords[mode], minlength=dims[mode])
         assert np.all(Y[lens == 0] == 0)
@@ -610,7 +610,7 @@ def test_ttmc_memo_pair(tk, dtype, case):
         Y = Y.double().cpu().numpy()
         Yo = oracle.ttmc(w.coords, w.vals, dims, ranks, mode, U)
         assert rel_fro(Y, Yo) <= TOL_Y[dtype], (mode, rel_fro(Y, Yo))
-        Yc = oracle.ttmc(w.coords, cast_vals(w.vals, dtype), dims, ranks, mode, cast_inputs(U, dtype))
+        Yc = oracle_ttmc_rounded(w.coords, w.vals, dims, ranks, mode, U, dtype)
         assert rel_fro(Y, Yc) <= (1e-13 if dtype == "f64" else 2e-6), (mode, rel_fro(Y, Yc))
     # the fiber table is kept: a second call with other factors gives their products
     Unext2 = rng.standard_normal((dims[a], ranks[a]))

@@ -111,6 +111,60 @@ def test_ttmc_threads_bit_identical(threads):
     assert all(np.array_equal(a, b) for a, b in zip(U1, Ut))
 
 
+def test_bf16_nearest_matches_torch():
+    """The oracle's BF16 rounding equals torch's CPU bfloat16 conversion (round to nearest, ties
+    to even) on values over many binades and on exact halfway cases of both parities."""
+    import torch
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal(20000) * np.exp2(rng.integers(-20, 20, 20000))).astype(np.float32).astype(np.float64)
+    # halfway cases: a BF16 number plus half its unit in the last place
+    b = torch.from_numpy(x[:5000]).to(torch.bfloat16).to(torch.float64).numpy()
+    _, e = np.frexp(b)
+    ties = b + np.ldexp(1.0, e - 9)
+    x = np.concatenate([x, ties, [0.0, 1.0, -1.0]])
+    ref = torch.from_numpy(x).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(oracle.bf16_nearest(x), ref)
+
+
+def test_ttmc_bf16_operands_exact_products_equal_ttmc():
+    """With power-of-two values and BF16 factors every product x a is a BF16 number, so the
+    BF16-operand TTMc equals the plain TTMc (which pins its contraction and column order)."""
+    rng = np.random.default_rng(8)
+    dims, ranks = [9, 7, 6], [3, 4, 2]
+    w = random_tensor(21, dims, 120, ranks)
+    vals = np.exp2(rng.integers(-3, 4, w.nnz)) * np.sign(rng.standard_normal(w.nnz))
+    U = [oracle.bf16_nearest(u) for u in w.U_init]
+    for n in range(3):
+        np.testing.assert_allclose(oracle.ttmc_bf16_operands(w.coords, vals, dims, ranks, n, U),
+                                   oracle.ttmc(w.coords, vals, dims, ranks, n, U), rtol=0, atol=1e-14)
+
+
+def test_ttmc_bf16_operands_brute_force():
+    """Against a loop over nonzeros with torch's BF16 rounding of x a: Y[i_n] += kron(bf16(x a), b);
+    and the rounding is within its bound of the plain TTMc (8 significant bits:
+    |bf16(v) - v| <= 2^-8 |v|)."""
+    import torch
+    dims, ranks = [6, 5, 7], [2, 3, 4]
+    w = random_tensor(23, dims, 60, ranks)
+    U = [oracle.bf16_nearest(u) for u in w.U_init]
+    vals = oracle.bf16_nearest(w.vals)
+    for n in range(3):
+        s, t = [k for k in range(3) if k != n]
+        Y = np.zeros((dims[n], ranks[s] * ranks[t]))
+        for p in range(w.nnz):
+            a = U[s][w.coords[s, p]] * vals[p]
+            a = torch.from_numpy(a).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+            Y[w.coords[n, p]] += np.kron(a, U[t][w.coords[t, p]])
+        got = oracle.ttmc_bf16_operands(w.coords, vals, dims, ranks, n, U)
+        np.testing.assert_allclose(got, Y, rtol=0, atol=1e-14)
+        plain = oracle.ttmc(w.coords, vals, dims, ranks, n, U)
+        assert np.abs(got - plain).max() > 0
+        bound = np.zeros_like(plain)
+        np.add.at(bound, w.coords[n], 2.0 ** -8 * np.abs(np.einsum("pi,pj->pij", U[s][w.coords[s]] * vals[:, None],
+                                                                    U[t][w.coords[t]]).reshape(w.nnz, -1)))
+        assert np.all(np.abs(got - plain) <= bound + 1e-15)
+
+
 # ------------------------------------------------------------------------------------------
 # QRP
 # ------------------------------------------------------------------------------------------
