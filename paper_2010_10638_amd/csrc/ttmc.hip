@@ -598,25 +598,30 @@ __global__ __launch_bounds__(256) void k_ttmc3_lds(TtmcArgs a, ResArgs res) {
 
 // Order-3 TTMc with BF16 operands on the BF16 matrix instruction (v_mfma_f32_16x16x32_bf16, 32
 // nonzeros per instruction).  That instruction takes, in lane l, eight consecutive values of the
-// contraction index (nonzeros 8(l/16)..+7) for one factor column l%16, so the wave's tile is kept
-// column-major: At[c][e] = bf16(x_e * a_e[c]) (the product of two BF16 numbers, exact in FP32, is
-// rounded once to BF16 as the tile is written) and Bt[c][e] = b_e[c].  The batch pipeline is that of
-// the FP32-tile kernel above (stream two batches ahead, rows gathered one batch ahead with 16-byte
-// loads, two lanes per 32-byte row); the gathered rows are transposed into the tile with 2-byte
-// LDS writes.  A batch that lies inside one row takes two MFMAs; a batch in which rows open takes
-// the 16 FP32 steps of four nonzeros each (v_mfma_f32_16x16x4f32 on the same tile values), writing
-// each finished row out before the step that opens the next.  Either way every product is
-// bf16(x a) * b, exact in FP32, and the sums are FP32.
-constexpr int kBfStride = 72;   // entries per tile column: 144-byte rows keep the 16-byte reads of
-                                // 16 columns on distinct banks
-
+// contraction index (nonzeros 8(l/16)..+7) for one factor column l%16, while a 16-byte gather holds
+// eight columns of one nonzero's row: the wave's tile stays entry-major (as gathered, with the A
+// row scaled: A[e] = bf16(x_e a_e), the product of two BF16 numbers exact in FP32 and rounded once
+// to BF16 as it is written) and the operands are read column-wise, 2 bytes per value.  The 32-byte
+// rows sit four to a 128-byte group with row e in slot (e & 3) ^ ((e >> 3) & 3), so that both the
+// 16-byte row writes and the column reads of 4 x 16 (entry, column) pairs fall on distinct banks.
+// The batch pipeline is that of the FP32-tile kernel above (stream two batches ahead, rows
+// gathered one batch ahead with 16-byte loads, two lanes per 32-byte row).  A batch that lies
+// inside one row takes two MFMAs; a batch in which rows open takes the 16 FP32 steps of four
+// nonzeros each (v_mfma_f32_16x16x4f32 on the same tile values), writing each finished row out
+// before the step that opens the next.  Either way every product is bf16(x a) * b, exact in FP32,
+// and the sums are FP32.
 struct BfTiles {
-    bf16_t At[16][kBfStride];
-    bf16_t Bt[16][kBfStride];
+    uint4 A[128];   // 64 rows of 16 BF16 values, swizzled (bf_off)
+    uint4 B[128];
     float x[64];
     int32_t ia[64];
     int32_t ib[64];
 };
+
+// byte offset of column c of entry e in a tile
+__device__ inline uint32_t bf_off(int e, int c) {
+    return 128u * (uint32_t)(e >> 2) + 32u * (uint32_t)((e & 3) ^ ((e >> 3) & 3)) + 2u * (uint32_t)c;
+}
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -691,23 +696,21 @@ __global__ __launch_bounds__(256) void k_ttmc3_bf(TtmcArgs a) {
         ga1 = *(const uint4*)(Fa + ((uint32_t)T.ia[r1] * (uint32_t)ROWB + part));
         gb1 = *(const uint4*)(Fb + ((uint32_t)T.ib[r1] * (uint32_t)ROWB + part));
     };
-    // transpose the gathered rows into the tile, a scaled by the entry's value
+    // the gathered rows into the tile (16 bytes per lane and factor), a scaled by the entry's value
     auto put_one = [&](const uint4& ua, const uint4& ub, int e) __attribute__((always_inline)) {
         const float xe = T.x[e];
-        const int c0 = 8 * (lane & 1);
         const uint32_t wa[4] = {ua.x, ua.y, ua.z, ua.w};
-        const uint32_t wb[4] = {ub.x, ub.y, ub.z, ub.w};
+        uint32_t pa[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float lo = __uint_as_float(wa[i] << 16) * xe;
             const float hi = __uint_as_float(wa[i] & 0xffff0000u) * xe;
             const bf16x2_t p = __builtin_convertvector((float __attribute__((ext_vector_type(2)))){lo, hi}, bf16x2_t);
-            const uint32_t pk = __builtin_bit_cast(uint32_t, p);
-            T.At[c0 + 2 * i][e] = (bf16_t)(pk & 0xffffu);
-            T.At[c0 + 2 * i + 1][e] = (bf16_t)(pk >> 16);
-            T.Bt[c0 + 2 * i][e] = (bf16_t)(wb[i] & 0xffffu);
-            T.Bt[c0 + 2 * i + 1][e] = (bf16_t)(wb[i] >> 16);
+            pa[i] = __builtin_bit_cast(uint32_t, p);
         }
+        const uint32_t off = bf_off(e, 8 * (lane & 1));
+        *(uint4*)((char*)T.A + off) = make_uint4(pa[0], pa[1], pa[2], pa[3]);
+        *(uint4*)((char*)T.B + off) = ub;
     };
     auto put = [&]() __attribute__((always_inline)) {
         put_one(ga0, gb0, lane >> 1);
@@ -746,8 +749,13 @@ __global__ __launch_bounds__(256) void k_ttmc3_bf(TtmcArgs a) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if (32 * j < q1 - p) {
-                    const bf16x8_t av = *(const bf16x8_t*)&T.At[m][32 * j + 8 * kq];
-                    const bf16x8_t bv = *(const bf16x8_t*)&T.Bt[m][32 * j + 8 * kq];
+                    bf16x8_t av, bv;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const uint32_t off = bf_off(32 * j + 8 * kq + i, m);
+                        av[i] = *(const __bf16*)((const char*)T.A + off);
+                        bv[i] = *(const __bf16*)((const char*)T.B + off);
+                    }
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
                 }
             }
@@ -760,8 +768,9 @@ __global__ __launch_bounds__(256) void k_ttmc3_bf(TtmcArgs a) {
                 float av[8], bv[8];
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
-                    av[t] = bf16_to_f32(T.At[m][4 * (t0 + t) + kq]);
-                    bv[t] = bf16_to_f32(T.Bt[m][4 * (t0 + t) + kq]);
+                    const uint32_t off = bf_off(4 * (t0 + t) + kq, m);
+                    av[t] = bf16_to_f32(*(const bf16_t*)((const char*)T.A + off));
+                    bv[t] = bf16_to_f32(*(const bf16_t*)((const char*)T.B + off));
                 }
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
