@@ -648,6 +648,27 @@ __global__ void k_syrk_rows(const YT* __restrict__ Y, int I, int K, double* __re
     A[e] = s;
 }
 
+// Y Y^T (I x I, FP64) for the fat rule, one wave per entry of the upper triangle: workgroup (x, y)
+// takes row a = y and columns b = 4x + w >= a; lanes read consecutive columns of rows a and b
+// (coalesced), the 64 partial sums are added by butterflies, and both A[a][b] and A[b][a] are
+// written.
+template <typename YT>
+__global__ __launch_bounds__(256) void k_syrk_waves(const YT* __restrict__ Y, int I, int K, double* __restrict__ A) {
+    const int lane = threadIdx.x & 63;
+    const int a = blockIdx.y;
+    const int b = 4 * blockIdx.x + (threadIdx.x >> 6);
+    if (b < a || b >= I) return;
+    const YT* ya = Y + (int64_t)a * K;
+    const YT* yb = Y + (int64_t)b * K;
+    double s = 0.0;
+    for (int c = lane; c < K; c += 64) s += (double)ya[c] * (double)yb[c];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) {
+        A[(int64_t)a * I + b] = s;
+        A[(int64_t)b * I + a] = s;
+    }
+}
+
 __device__ inline double block_sum(double v, double* red) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     __syncthreads();
@@ -663,7 +684,7 @@ __device__ inline double block_sum(double v, double* red) {
 // the rows i0 + w, i0 + w + nw, ...; the per-wave partials are added in wave order.
 // emit(c, s, valid) runs on the 64 lanes of wave 0 for every block (valid: c < n).
 template <typename F, typename E>
-__device__ inline void column_sums(int64_t i0, int64_t m, int c0, int n, double* part, F f, E emit) {
+__device__ __attribute__((always_inline)) inline void column_sums(int64_t i0, int64_t m, int c0, int n, double* part, F f, E emit) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = (int)(blockDim.x >> 6);
     for (int cb = c0; cb < n; cb += 64) {
         const int c = cb + lane;
@@ -683,8 +704,26 @@ __device__ inline void column_sums(int64_t i0, int64_t m, int c0, int n, double*
 
 // Eager Householder QRP on A (m x n, FP64, in place), R steps, by one workgroup (any size up to
 // 1024 threads), then Q[:, :R] = H_0 ... H_{R-1} [I; 0] into U (m x R) and the low-precision copy.
+// f(i, c) for the entries e = tid, tid + nt, ... of a rows x cols block in row-major order, the
+// (row, column) pair stepped incrementally after one division per thread
+template <typename F>
+__device__ __attribute__((always_inline)) inline void for_block(int64_t rows, int64_t cols, F f) {
+    const int nt = (int)blockDim.x;
+    if (rows <= 0 || cols <= 0) return;
+    int64_t r = threadIdx.x / cols, c = threadIdx.x % cols;
+    const int64_t dr = nt / cols, dc = nt % cols;
+    for (; r < rows; r += dr, c += dc) {
+        if (c >= cols) {
+            c -= cols;
+            ++r;
+            if (r >= rows) break;
+        }
+        f(r, c);
+    }
+}
+
 template <typename YT, typename LT>
-__device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ A, int64_t m, int n, int R,
+__device__ __attribute__((always_inline)) void house_qrp_body(const YT* __restrict__ src, double* __restrict__ A, int64_t m, int n, int R,
                                double* __restrict__ V, double* __restrict__ w,
                                double* __restrict__ beta_s, int32_t* __restrict__ perm,
                                double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
@@ -760,37 +799,34 @@ __device__ void house_qrp_body(const YT* __restrict__ src, double* __restrict__ 
         __syncthreads();
         column_sums(j, m, j, n, part, [&](int64_t i, int c) { return V[i * R + j] * A[i * n + c]; },
                     [&](int c, double v, bool valid) { if (valid) w[c] = beta * v; });
-        const int64_t cols = n - j;
-        for (int64_t e = tid; e < (m - j) * cols; e += nt) {
-            const int64_t i = j + e / cols;
-            const int c = j + (int)(e % cols);
+        for_block(m - j, n - j, [&](int64_t r, int64_t cc) {
+            const int64_t i = j + r;
+            const int c = j + (int)cc;
             A[i * n + c] -= V[i * R + j] * w[c];
-        }
+        });
         __syncthreads();
     }
     // Q = H_0 ... H_{R-1} [I; 0]
-    for (int64_t e = tid; e < m * R; e += nt) U[e] = ((e / R) == (e % R)) ? 1.0 : 0.0;
+    for_block(m, R, [&](int64_t i, int64_t c) { U[i * R + c] = (i == c) ? 1.0 : 0.0; });
     __syncthreads();
     for (int j = R - 1; j >= 0; --j) {
         const double beta = beta_s[j];
         if (beta == 0.0) continue;
         column_sums(j, m, 0, R, part, [&](int64_t i, int c) { return V[i * R + j] * U[i * R + c]; },
                     [&](int c, double v, bool valid) { if (valid) w[c] = beta * v; });
-        for (int64_t e = tid; e < (m - j) * R; e += nt) {
-            const int64_t i = j + e / R;
-            const int c = (int)(e % R);
+        for_block(m - j, R, [&](int64_t r, int64_t c) {
+            const int64_t i = j + r;
             U[i * R + c] -= V[i * R + j] * w[c];
-        }
+        });
         __syncthreads();
     }
-    for (int64_t e = tid; e < m * ldlp; e += nt) {
-        const int64_t i = e / ldlp;
-        const int c = (int)(e % ldlp);
+    for_block(m, ldlp, [&](int64_t i, int64_t c) {
+        const int64_t e = i * ldlp + c;
         const double u = (c < R) ? U[i * R + c] : 0.0;
         if constexpr (sizeof(LT) == 8) Ulp[e] = u;
         else if constexpr (sizeof(LT) == 4) Ulp[e] = (float)u;
         else Ulp[e] = f32_to_bf16((float)u);
-    }
+    });
     if (piv_out && tid < R) piv_out[tid] = perm[tid];
 }
 
@@ -801,6 +837,33 @@ __global__ __launch_bounds__(1024) void k_house_qrp(const YT* __restrict__ src, 
                                                     double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
                                                     int32_t* __restrict__ piv_out, double* __restrict__ gaps) {
     house_qrp_body<YT, LT>(src, A, m, n, R, V, w, beta_s, perm, U, Ulp, ldlp, piv_out, gaps);
+}
+
+// The same with every working array in LDS (dynamic shared memory, at most kHouseLdsBytes): the
+// matrix (m n doubles, from Y = src or, for the fat rule, the Y Y^T already formed in A), the
+// reflectors V (m R), w, the betas and the Q being formed (m R), which is copied to U at the end
+constexpr size_t kHouseLdsBytes = 120 * 1024;
+
+inline size_t house_lds_bytes(int64_t m, int n, int R) {
+    return (size_t)(m * n + 2 * m * R + std::max(n, R) + R) * sizeof(double);
+}
+
+template <typename YT, typename LT>
+__global__ __launch_bounds__(1024) void k_house_qrp_lds(const YT* __restrict__ src, const double* __restrict__ A,
+                                                        int64_t m, int n, int R, int32_t* __restrict__ perm,
+                                                        double* __restrict__ U, LT* __restrict__ Ulp, int ldlp,
+                                                        int32_t* __restrict__ piv_out, double* __restrict__ gaps) {
+    extern __shared__ double house_lds[];
+    double* Al = house_lds;
+    double* Vl = Al + m * n;
+    double* wl = Vl + m * R;
+    double* bl = wl + max(n, R);
+    double* Ul = bl + R;
+    for (int64_t e = threadIdx.x; e < m * n; e += blockDim.x) Al[e] = src ? yld(src, e) : A[e];
+    __syncthreads();
+    house_qrp_body<YT, LT>(nullptr, Al, m, n, R, Vl, wl, bl, perm, Ul, Ulp, ldlp, piv_out, gaps);
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < m * R; e += blockDim.x) U[e] = Ul[e];
 }
 
 // The same Householder QRP spread over the whole grid (cooperative launch, grid barriers between
@@ -1269,11 +1332,27 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
         hgaps = nullptr;
     }
     if (p.route == 2) {
-        k_syrk_rows<YT><<<cdiv(I * I, 256), 256, 0, s>>>(Y, (int)I, (int)K, W + p.o_A);
-        TK_LAUNCH_CHECK("k_syrk_rows");
+        if (I <= 65535) {
+            k_syrk_waves<YT><<<dim3(cdiv(I, 4), (unsigned)I), 256, 0, s>>>(Y, (int)I, (int)K, W + p.o_A);
+            TK_LAUNCH_CHECK("k_syrk_waves");
+        } else {
+            k_syrk_rows<YT><<<cdiv(I * I, 256), 256, 0, s>>>(Y, (int)I, (int)K, W + p.o_A);
+            TK_LAUNCH_CHECK("k_syrk_rows");
+        }
     }
     if (p.grid)
         return launch_house_grid<YT, LT>(ctx, p, p.route == 2 ? nullptr : Y, W, perm, U, Ulp, ldlp, piv, hgaps, nullptr, s);
+    const size_t lbytes = house_lds_bytes(p.m, p.n, p.R);
+    static int lds_ok = -1;   // whether the LDS kernel may take kHouseLdsBytes of dynamic LDS: asked once
+    if (lds_ok < 0)
+        lds_ok = hipFuncSetAttribute((const void*)k_house_qrp_lds<YT, LT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kHouseLdsBytes) == hipSuccess;
+    if (lds_ok && lbytes <= kHouseLdsBytes) {
+        k_house_qrp_lds<YT, LT><<<1, 1024, lbytes, s>>>(p.route == 2 ? nullptr : Y, W + p.o_A, p.m, p.n, p.R, perm, U,
+                                                        Ulp, ldlp, piv, hgaps);
+        TK_LAUNCH_CHECK("k_house_qrp_lds");
+        return TK_OK;
+    }
     k_house_qrp<YT, LT><<<1, 1024, 0, s>>>(p.route == 2 ? nullptr : Y, W + p.o_A, p.m, p.n, p.R, W + p.o_V, W + p.o_w,
                                            W + p.o_beta, perm, U, Ulp, ldlp, piv, hgaps);
     TK_LAUNCH_CHECK("k_house_qrp");
@@ -1304,8 +1383,13 @@ int gram_typed(tk_ctx* ctx, int mode, const YT* Y, double** A, int* n, hipStream
     }
     if (p.route == 2) {
         const int64_t I = ctx->dims[mode];
-        k_syrk_rows<YT><<<cdiv(I * I, 256), 256, 0, s>>>(Y, (int)I, (int)ctx->mode[mode].K, W + p.o_A);
-        TK_LAUNCH_CHECK("k_syrk_rows");
+        if (I <= 65535) {
+            k_syrk_waves<YT><<<dim3(cdiv(I, 4), (unsigned)I), 256, 0, s>>>(Y, (int)I, (int)ctx->mode[mode].K, W + p.o_A);
+            TK_LAUNCH_CHECK("k_syrk_waves");
+        } else {
+            k_syrk_rows<YT><<<cdiv(I * I, 256), 256, 0, s>>>(Y, (int)I, (int)ctx->mode[mode].K, W + p.o_A);
+            TK_LAUNCH_CHECK("k_syrk_rows");
+        }
         *A = W + p.o_A;
         *n = (int)I;
         return TK_OK;
