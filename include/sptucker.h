@@ -53,8 +53,11 @@ enum tk_status {
 /* Arithmetic of the TTMc (the QRP, core and fit always run in FP64):
  *   TK_F64  - FP64 values, factors, products and accumulation; Y_(n) is double.
  *   TK_F32  - FP32 values and factor copies, FP32 products and accumulation; Y_(n) is float.
- *   TK_BF16 - BF16 values and factor copies, FP32 products (exact: a product of three bf16
- *             numbers fits the fp32 significand) and FP32 accumulation; Y_(n) is float. */
+ *   TK_BF16 - BF16 values and factor copies and FP32 accumulation; Y_(n) is float.  Order 3
+ *             (both other ranks <= 16) runs on the BF16 matrix instruction: x a is rounded
+ *             once to BF16 (nearest, ties to even) and multiplied by b exactly in FP32.  Other
+ *             orders take FP32 products (exact: a product of three bf16 numbers fits the fp32
+ *             significand). */
 enum tk_dtype { TK_F64 = 0, TK_F32 = 1, TK_BF16 = 2 };
 
 /* tucker_init flags */
