@@ -307,6 +307,8 @@ def qrp_case(tk, dtype, dims, ranks, mode, nnz, seed, fat_rule=True):
     ([400, 40, 40], [34, 6, 6], 0, 8000),     # R > 32: Householder route
     ([1500, 60, 50], [8, 40, 30], 0, 30000),  # K = 1200 > 1024: Householder route
     ([20, 30, 25, 40], [5, 4, 4, 4], 0, 6000),  # fat (K = 64 > 20): Householder on Y Y^T
+    ([110, 20, 20, 20], [5, 5, 5, 5], 0, 30000),  # fat, Y Y^T 110 x 110: one workgroup, arrays in LDS
+    ([200, 20, 20, 20], [6, 6, 6, 6], 0, 40000),  # fat, Y Y^T 200 x 200: beyond the LDS limit, global memory
 ])
 def test_qrp_parity(tk, dtype, case):
     dims, ranks, mode, nnz = case
