@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, 
 // n x n partial (entries of upper block pairs only).
 template <typename YT>
 __global__ __launch_bounds__(256, 2) void k_gram_rows(const YT* __restrict__ Y, int64_t m, int n,
-                                                      int nb, int64_t slab, double* __restrict__ part) {
+                                                      int nb, int64_t slab, bool off32, double* __restrict__ part) {
     constexpr int kStage = 2 * 32 * 65 * (int)sizeof(YT);
     static_assert(2 * kStage >= 64 * 64 * (int)sizeof(double), "the reduction reuses the staging LDS");
     __shared__ __align__(16) char lds[2 * kStage];
@@ -110,20 +110,45 @@ __global__ __launch_bounds__(256, 2) void k_gram_rows(const YT* __restrict__ Y, 
     d4_t acc[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc[t] = d4_t{0, 0, 0, 0};
+    // this thread's share of a chunk: column cc of each panel, rows rw + 4k (k < 8).  Full chunks
+    // load from 32-bit byte offsets off a uniform base (off32: the whole Y below 4 GB); the last,
+    // partial chunk takes the clamped loads of the shared A^T B block.
+    const int cc = threadIdx.x & 63, rw = threadIdx.x >> 6;
+    const bool oka = bi * 64 + cc < n, okb = bj * 64 + cc < n;
+    const uint32_t ca = (uint32_t)(bi * 64 + (oka ? cc : 0)), cb = (uint32_t)(bj * 64 + (okb ? cc : 0));
+    const uint32_t rowb = (uint32_t)n * (uint32_t)sizeof(YT);   // bytes per row of Y
     YT xa[8], xb[8];
-    atb_stage(Y, n, n, Y, n, n, r0, r1, bi * 64, bj * 64, xa, xb);
+    auto stage = [&](int64_t row0) __attribute__((always_inline)) {
+        if (off32 && row0 + 32 <= r1) {
+            const uint32_t o = (uint32_t)(row0 + rw) * rowb;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                xa[k] = *(const YT*)((const char*)Y + (o + 4u * (uint32_t)k * rowb + ca * (uint32_t)sizeof(YT)));
+                xb[k] = *(const YT*)((const char*)Y + (o + 4u * (uint32_t)k * rowb + cb * (uint32_t)sizeof(YT)));
+            }
+        } else {
+            atb_stage(Y, n, n, Y, n, n, row0, r1, bi * 64, bj * 64, xa, xb);
+        }
+    };
+    stage(r0);
     int buf = 0;
     for (int64_t row0 = r0; row0 < r1; row0 += 32) {
+        if (row0 + 32 <= r1) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = threadIdx.x + 256 * k;
-            const int rr = e >> 6, cc = e & 63;
-            const bool rv = row0 + rr < r1;
-            As[buf][rr][cc] = (rv && bi * 64 + cc < n) ? xa[k] : YT(0);
-            Bs[buf][rr][cc] = (rv && bj * 64 + cc < n) ? xb[k] : YT(0);
+            for (int k = 0; k < 8; ++k) {
+                As[buf][rw + 4 * k][cc] = oka ? xa[k] : YT(0);
+                Bs[buf][rw + 4 * k][cc] = okb ? xb[k] : YT(0);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const bool rv = row0 + rw + 4 * k < r1;
+                As[buf][rw + 4 * k][cc] = (rv && oka) ? xa[k] : YT(0);
+                Bs[buf][rw + 4 * k][cc] = (rv && okb) ? xb[k] : YT(0);
+            }
         }
         __syncthreads();
-        if (row0 + 32 < r1) atb_stage(Y, n, n, Y, n, n, row0 + 32, r1, bi * 64, bj * 64, xa, xb);
+        if (row0 + 32 < r1) stage(row0 + 32);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int rr = 8 * w + 4 * h + kq;
@@ -179,7 +204,10 @@ template <typename YT>
 void launch_gram_partial(const YT* Y, int64_t m, int n, int nb, int nsplit, int64_t slab, double* part,
                          hipStream_t s) {
     const dim3 g((unsigned)(nb * (nb + 1) / 2), (unsigned)nsplit);
-    if (nb <= 2) k_gram_rows<YT><<<g, 256, 0, s>>>(Y, m, n, nb, slab, part);
+    if (nb <= 2) {
+        const bool off32 = (uint64_t)m * (uint64_t)n * sizeof(YT) < (1ull << 32);
+        k_gram_rows<YT><<<g, 256, 0, s>>>(Y, m, n, nb, slab, off32, part);
+    }
     else k_gram_partial<YT><<<g, 256, 0, s>>>(Y, m, n, nb, slab, part);
 }
 
