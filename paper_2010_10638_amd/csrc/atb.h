@@ -37,21 +37,49 @@ __device__ void atb_block(const AT* __restrict__ A, int lda, int na, const BT* _
                           BT (*Bs)[32][65], atb_d4_t* acc) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int kq = lane >> 4, c16 = lane & 15;
+    // this thread's share of a chunk: column cc of each panel, rows rw + 4k (k < 8).  Full chunks
+    // load from 32-bit byte offsets off a uniform base when both matrices' rows below r1 span less
+    // than 4 GB; the last, partial chunk (and larger inputs) take the clamped loads above.
+    const int cc = lane, rw = w;
+    const bool oka = a0 + cc < na, okb = b0 + cc < nbc;
+    const uint32_t ca = (uint32_t)(oka ? a0 + cc : a0) * (uint32_t)sizeof(AT);
+    const uint32_t cb = (uint32_t)(okb ? b0 + cc : b0) * (uint32_t)sizeof(BT);
+    const uint32_t rowa = (uint32_t)lda * (uint32_t)sizeof(AT), rowb = (uint32_t)ldb * (uint32_t)sizeof(BT);
+    const bool off32 = (uint64_t)r1 * (uint64_t)lda * sizeof(AT) < (1ull << 32) &&
+                       (uint64_t)r1 * (uint64_t)ldb * sizeof(BT) < (1ull << 32);
     AT xa[8];
     BT xb[8];
-    atb_stage(A, lda, na, B, ldb, nbc, r0, r1, a0, b0, xa, xb);
+    auto stage = [&](int64_t row0) __attribute__((always_inline)) {
+        if (off32 && row0 + 32 <= r1) {
+            const uint32_t r = (uint32_t)(row0 + rw);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                xa[k] = *(const AT*)((const char*)A + ((r + 4u * (uint32_t)k) * rowa + ca));
+                xb[k] = *(const BT*)((const char*)B + ((r + 4u * (uint32_t)k) * rowb + cb));
+            }
+        } else {
+            atb_stage(A, lda, na, B, ldb, nbc, row0, r1, a0, b0, xa, xb);
+        }
+    };
+    stage(r0);
     int buf = 0;
     for (int64_t row0 = r0; row0 < r1; row0 += 32) {
+        if (row0 + 32 <= r1) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = threadIdx.x + 256 * k;
-            const int rr = e >> 6, cc = e & 63;
-            const bool rv = row0 + rr < r1;
-            As[buf][rr][cc] = (rv && a0 + cc < na) ? xa[k] : AT(0);
-            Bs[buf][rr][cc] = (rv && b0 + cc < nbc) ? xb[k] : BT(0);
+            for (int k = 0; k < 8; ++k) {
+                As[buf][rw + 4 * k][cc] = oka ? xa[k] : AT(0);
+                Bs[buf][rw + 4 * k][cc] = okb ? xb[k] : BT(0);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const bool rv = row0 + rw + 4 * k < r1;
+                As[buf][rw + 4 * k][cc] = (rv && oka) ? xa[k] : AT(0);
+                Bs[buf][rw + 4 * k][cc] = (rv && okb) ? xb[k] : BT(0);
+            }
         }
         __syncthreads();
-        if (row0 + 32 < r1) atb_stage(A, lda, na, B, ldb, nbc, row0 + 32, r1, a0, b0, xa, xb);
+        if (row0 + 32 < r1) stage(row0 + 32);
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
             const int rr = 4 * st + kq;
