@@ -72,6 +72,80 @@ __global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, 
         }
 }
 
+// The chunk loop of k_gram_rows for one pair shape (see there): LA / LB live 16-column tiles of
+// the two panels; a diagonal pair stages one panel and reads both operands from it.  Each thread
+// stages column cc of each panel for rows rw + 4k (k < 8) of a 32-row chunk; full chunks load from
+// 32-bit byte offsets off a uniform base (off32: the whole Y below 4 GB), the last, partial chunk
+// clamped loads.
+template <typename YT, int LA, int LB, bool DIAG>
+__device__ __attribute__((always_inline)) inline void gram_rows_loop(const YT* __restrict__ Y, int n, int bi, int bj,
+                                                                     int64_t r0, int64_t r1, bool off32,
+                                                                     YT (*As)[32][65], YT (*Bs)[32][65], d4_t* acc) {
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int kq = lane >> 4, c16 = lane & 15;
+    const int cc = lane, rw = w;
+    const bool oka = bi * 64 + cc < n, okb = bj * 64 + cc < n;
+    const uint32_t ca = (uint32_t)(bi * 64 + (oka ? cc : 0)), cb = (uint32_t)(bj * 64 + (okb ? cc : 0));
+    const uint32_t rowb = (uint32_t)n * (uint32_t)sizeof(YT);   // bytes per row of Y
+    YT xa[8], xb[8];
+    auto stage = [&](int64_t row0) __attribute__((always_inline)) {
+        if (off32 && row0 + 32 <= r1) {
+            const uint32_t o = (uint32_t)(row0 + rw) * rowb;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                xa[k] = *(const YT*)((const char*)Y + (o + 4u * (uint32_t)k * rowb + ca * (uint32_t)sizeof(YT)));
+                if constexpr (!DIAG)
+                    xb[k] = *(const YT*)((const char*)Y + (o + 4u * (uint32_t)k * rowb + cb * (uint32_t)sizeof(YT)));
+            }
+        } else {
+            // clamped rows (the row past r1 repeats row r1 - 1 and is masked when staged)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int64_t row = min(row0 + rw + 4 * k, r1 - 1);
+                xa[k] = Y[row * n + ca];
+                if constexpr (!DIAG) xb[k] = Y[row * n + cb];
+            }
+        }
+    };
+    stage(r0);
+    int buf = 0;
+    for (int64_t row0 = r0; row0 < r1; row0 += 32) {
+        const bool full = row0 + 32 <= r1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool rv = full || row0 + rw + 4 * k < r1;
+            As[buf][rw + 4 * k][cc] = (rv && oka) ? xa[k] : YT(0);
+            if constexpr (!DIAG) Bs[buf][rw + 4 * k][cc] = (rv && okb) ? xb[k] : YT(0);
+        }
+        __syncthreads();
+        if (row0 + 32 < r1) stage(row0 + 32);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int rr = 8 * w + 4 * h + kq;
+            double av[4], bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t < LA) av[t] = (double)As[buf][rr][16 * t + c16];
+                if constexpr (!DIAG) {
+                    if (t < LB) bv[t] = (double)Bs[buf][rr][16 * t + c16];
+                } else {
+                    bv[t] = av[t];
+                }
+            }
+#define TK_GM(ti, tj)                                                                               \
+    if constexpr ((ti) < LA && (tj) < LB && (!DIAG || (ti) <= (tj)))                                \
+        acc[4 * (ti) + (tj)] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[4 * (ti) + (tj)], 0, 0, 0);
+            TK_GM(0, 0) TK_GM(0, 1) TK_GM(0, 2) TK_GM(0, 3)
+            TK_GM(1, 0) TK_GM(1, 1) TK_GM(1, 2) TK_GM(1, 3)
+            TK_GM(2, 0) TK_GM(2, 1) TK_GM(2, 2) TK_GM(2, 3)
+            TK_GM(3, 0) TK_GM(3, 1) TK_GM(3, 2) TK_GM(3, 3)
+#undef TK_GM
+        }
+        buf ^= 1;
+    }
+}
+
 // Partial C over one slab of rows for Y of at most 128 columns (one or two 64-column blocks, up
 // to three block pairs).  Rows come in chunks of 32, staged through LDS in Y's precision (the next
 // chunk's loads in flight during the current one); wave w takes the 4-row steps 2w and 2w+1 of
@@ -110,62 +184,23 @@ __global__ __launch_bounds__(256, 2) void k_gram_rows(const YT* __restrict__ Y, 
     d4_t acc[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc[t] = d4_t{0, 0, 0, 0};
-    // this thread's share of a chunk: column cc of each panel, rows rw + 4k (k < 8).  Full chunks
-    // load from 32-bit byte offsets off a uniform base (off32: the whole Y below 4 GB); the last,
-    // partial chunk takes the clamped loads of the shared A^T B block.
-    const int cc = threadIdx.x & 63, rw = threadIdx.x >> 6;
-    const bool oka = bi * 64 + cc < n, okb = bj * 64 + cc < n;
-    const uint32_t ca = (uint32_t)(bi * 64 + (oka ? cc : 0)), cb = (uint32_t)(bj * 64 + (okb ? cc : 0));
-    const uint32_t rowb = (uint32_t)n * (uint32_t)sizeof(YT);   // bytes per row of Y
-    YT xa[8], xb[8];
-    auto stage = [&](int64_t row0) __attribute__((always_inline)) {
-        if (off32 && row0 + 32 <= r1) {
-            const uint32_t o = (uint32_t)(row0 + rw) * rowb;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                xa[k] = *(const YT*)((const char*)Y + (o + 4u * (uint32_t)k * rowb + ca * (uint32_t)sizeof(YT)));
-                xb[k] = *(const YT*)((const char*)Y + (o + 4u * (uint32_t)k * rowb + cb * (uint32_t)sizeof(YT)));
-            }
-        } else {
-            atb_stage(Y, n, n, Y, n, n, row0, r1, bi * 64, bj * 64, xa, xb);
+    // the chunk loop, compiled per pair shape: LA / LB live 16-column tiles in the two panels, and
+    // a diagonal pair (one panel, upper tiles only)
+    const int la = min(4, (n - 64 * bi + 15) / 16), lb = min(4, (n - 64 * bj + 15) / 16);
+    if (diag) {
+        switch (la) {
+            case 1: gram_rows_loop<YT, 1, 1, true>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
+            case 2: gram_rows_loop<YT, 2, 2, true>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
+            case 3: gram_rows_loop<YT, 3, 3, true>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
+            default: gram_rows_loop<YT, 4, 4, true>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
         }
-    };
-    stage(r0);
-    int buf = 0;
-    for (int64_t row0 = r0; row0 < r1; row0 += 32) {
-        if (row0 + 32 <= r1) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                As[buf][rw + 4 * k][cc] = oka ? xa[k] : YT(0);
-                Bs[buf][rw + 4 * k][cc] = okb ? xb[k] : YT(0);
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const bool rv = row0 + rw + 4 * k < r1;
-                As[buf][rw + 4 * k][cc] = (rv && oka) ? xa[k] : YT(0);
-                Bs[buf][rw + 4 * k][cc] = (rv && okb) ? xb[k] : YT(0);
-            }
+    } else {   // bi = 0, bj = 1: the first panel is full
+        switch (lb) {
+            case 1: gram_rows_loop<YT, 4, 1, false>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
+            case 2: gram_rows_loop<YT, 4, 2, false>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
+            case 3: gram_rows_loop<YT, 4, 3, false>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
+            default: gram_rows_loop<YT, 4, 4, false>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
         }
-        __syncthreads();
-        if (row0 + 32 < r1) stage(row0 + 32);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int rr = 8 * w + 4 * h + kq;
-            double av[4], bv[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                av[t] = (double)As[buf][rr][16 * t + c16];
-                bv[t] = (double)Bs[buf][rr][16 * t + c16];
-            }
-#pragma unroll
-            for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < 4; ++tj)
-                    if (live & (1u << (4 * ti + tj)))
-                        acc[4 * ti + tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[4 * ti + tj], 0, 0, 0);
-        }
-        buf ^= 1;
     }
     // the four waves' sums, added in wave order through LDS: red[tile][v][lane]
     __syncthreads();
