@@ -25,7 +25,6 @@
 #include <hip/hip_cooperative_groups.h>
 
 #include "internal.h"
-#include "atb.h"
 
 namespace tk {
 
@@ -39,38 +38,6 @@ template <typename YT>
 __device__ inline double yld(const YT* Y, int64_t i) { return (double)Y[i]; }
 
 // ---- Route 0 -------------------------------------------------------------------------------
-
-// Partial C for one 64x64 block pair (bi <= bj) over one slab of rows.  Wave w computes the 16
-// rows bi*64+16w.. of the block, 4 MFMA tiles across bj's 64 columns.  In v_mfma_f64_16x16x4f64
-// lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds D[l/16 + 4v][l%16] in result v.
-// Gram partials: blockIdx.x enumerates the upper block pairs (bi <= bj) of 64-column blocks,
-// blockIdx.y the row slab.  part[split] holds the n x n partial (only upper-pair entries written).
-template <typename YT>
-__global__ __launch_bounds__(256) void k_gram_partial(const YT* __restrict__ Y, int64_t m, int n,
-                                                      int nb, int64_t slab, double* __restrict__ part) {
-    __shared__ YT As[2][32][65];
-    __shared__ YT Bs[2][32][65];
-    int b = blockIdx.x, bi = 0;
-    while (b >= nb - bi) { b -= nb - bi; ++bi; }
-    const int bj = bi + b;
-    const int64_t r0 = (int64_t)blockIdx.y * slab;
-    const int64_t r1 = min(m, r0 + slab);
-    d4_t acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = d4_t{0, 0, 0, 0};
-    atb_block<YT, YT>(Y, n, n, Y, n, n, r0, r1, bi * 64, bj * 64, As, Bs, acc);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int kq = lane >> 4, c16 = lane & 15;
-    double* P = part + (int64_t)blockIdx.y * n * n;
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = bi * 64 + 16 * w + kq + 4 * v;
-            const int j = bj * 64 + 16 * t + c16;
-            if (i < n && j < n) P[(int64_t)i * n + j] = acc[t][v];
-        }
-}
 
 // The chunk loop of k_gram_rows for one pair shape (see there): LA / LB live 16-column tiles of
 // the two panels; a diagonal pair stages one panel and reads both operands from it.  Each thread
@@ -146,9 +113,9 @@ __device__ __attribute__((always_inline)) inline void gram_rows_loop(const YT* _
     }
 }
 
-// Partial C over one slab of rows for Y of at most 128 columns (one or two 64-column blocks, up
-// to three block pairs).  Rows come in chunks of 32, staged through LDS in Y's precision (the next
-// chunk's loads in flight during the current one); wave w takes the 4-row steps 2w and 2w+1 of
+// Partial C = Y^T Y over one slab of rows for one upper pair (bi <= bj) of 64-column blocks.  Rows
+// come in chunks of 32, staged through LDS in Y's precision (the next chunk's loads in flight
+// during the current one); wave w takes the 4-row steps 2w and 2w+1 of
 // each chunk and accumulates all 16 16x16 tiles of the pair for them, so that per step a lane
 // reads 4 + 4 operands for up to 16 v_mfma_f64_16x16x4f64 (lane l supplies A[l%16][l/16] and
 // B[l/16][l%16] and holds D[l/16 + 4v][l%16] in result v).  Tiles that start at or past column n
@@ -194,7 +161,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_rows(const YT* __restrict__ Y, 
             case 3: gram_rows_loop<YT, 3, 3, true>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
             default: gram_rows_loop<YT, 4, 4, true>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
         }
-    } else {   // bi = 0, bj = 1: the first panel is full
+    } else {   // bi < bj: the first panel is full
         switch (lb) {
             case 1: gram_rows_loop<YT, 4, 1, false>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
             case 2: gram_rows_loop<YT, 4, 2, false>(Y, n, bi, bj, r0, r1, off32, As, Bs, acc); break;
@@ -233,17 +200,13 @@ __global__ __launch_bounds__(256, 2) void k_gram_rows(const YT* __restrict__ Y, 
     }
 }
 
-// Gram partials of Y (m x n) into part[nsplit][n][n]: the row-split kernel for n <= 128, the
-// tile-row kernel above it
+// Gram partials of Y (m x n) into part[nsplit][n][n]
 template <typename YT>
 void launch_gram_partial(const YT* Y, int64_t m, int n, int nb, int nsplit, int64_t slab, double* part,
                          hipStream_t s) {
     const dim3 g((unsigned)(nb * (nb + 1) / 2), (unsigned)nsplit);
-    if (nb <= 2) {
-        const bool off32 = (uint64_t)m * (uint64_t)n * sizeof(YT) < (1ull << 32);
-        k_gram_rows<YT><<<g, 256, 0, s>>>(Y, m, n, nb, slab, off32, part);
-    }
-    else k_gram_partial<YT><<<g, 256, 0, s>>>(Y, m, n, nb, slab, part);
+    const bool off32 = (uint64_t)m * (uint64_t)n * sizeof(YT) < (1ull << 32);
+    k_gram_rows<YT><<<g, 256, 0, s>>>(Y, m, n, nb, slab, off32, part);
 }
 
 // Sums the partials of entries in upper block pairs (bi <= bj) in split order and writes both
