@@ -209,16 +209,25 @@ void launch_gram_partial(const YT* Y, int64_t m, int n, int nb, int nsplit, int6
     k_gram_rows<YT><<<g, 256, 0, s>>>(Y, m, n, nb, slab, off32, part);
 }
 
-// Sums the partials of entries in upper block pairs (bi <= bj) in split order and writes both
-// C[i][j] and its mirror C[j][i].
-__global__ void k_gram_reduce(const double* __restrict__ part, int nsplit, int n, double* __restrict__ C) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n * n) return;
-    const int i = (int)(e / n), j = (int)(e % n);
-    if ((i >> 6) > (j >> 6)) return;
-    const double s = sum_strided(part + e, nsplit, (int64_t)n * n);
-    C[e] = s;
-    if ((i >> 6) != (j >> 6)) C[(int64_t)j * n + i] = s;
+// Sums the partials of entries in upper block pairs (bi <= bj) and writes both C[i][j] and its
+// mirror C[j][i].  A workgroup of 4 waves takes 64 entries: wave w adds the splits w, w + 4, ... in order, and the
+// four sums are added in wave order (every entry in the same order, so equal columns give equal
+// sums).
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int nsplit, int n,
+                                                     double* __restrict__ C) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t nn = (int64_t)n * n;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+    const bool ok = e < nn && ((int)(e / n) >> 6) <= ((int)(e % n) >> 6);
+    red[w][lane] = (ok && w < nsplit) ? sum_strided(part + w * nn + e, (nsplit - w + 3) / 4, 4 * nn) : 0.0;
+    __syncthreads();
+    if (w == 0 && ok) {
+        const double s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        const int i = (int)(e / n), j = (int)(e % n);
+        C[e] = s;
+        if ((i >> 6) != (j >> 6)) C[(int64_t)j * n + i] = s;
+    }
 }
 
 // Wave-wide maximum / minimum, the result in every lane: butterflies inside each row of 16 lanes
@@ -1310,7 +1319,7 @@ int run_typed(tk_ctx* ctx, int mode, const YT* Y, double* U, int32_t* piv, hipSt
     if (p.route == 0) {
         launch_gram_partial<YT>(Y, p.m, p.n, p.nb, p.nsplit, p.slab, W + p.o_part, s);
         TK_LAUNCH_CHECK("k_gram_partial");
-        k_gram_reduce<<<cdiv((int64_t)p.n * p.n, 256), 256, 0, s>>>(W + p.o_part, p.nsplit, p.n, W + p.o_C);
+        k_gram_reduce<<<cdiv((int64_t)p.n * p.n, 64), 256, 0, s>>>(W + p.o_part, p.nsplit, p.n, W + p.o_C);
         TK_LAUNCH_CHECK("k_gram_reduce");
         const size_t lsz = (size_t)p.n * p.R * sizeof(double);
         const unsigned nthr = (unsigned)std::max(64, (p.n + 63) / 64 * 64);
@@ -1401,7 +1410,7 @@ int gram_typed(tk_ctx* ctx, int mode, const YT* Y, double** A, int* n, hipStream
     if (p.route == 0) {
         launch_gram_partial<YT>(Y, p.m, p.n, p.nb, p.nsplit, p.slab, W + p.o_part, s);
         TK_LAUNCH_CHECK("k_gram_partial");
-        k_gram_reduce<<<cdiv((int64_t)p.n * p.n, 256), 256, 0, s>>>(W + p.o_part, p.nsplit, p.n, W + p.o_C);
+        k_gram_reduce<<<cdiv((int64_t)p.n * p.n, 64), 256, 0, s>>>(W + p.o_part, p.nsplit, p.n, W + p.o_C);
         TK_LAUNCH_CHECK("k_gram_reduce");
         *A = W + p.o_C;
         *n = p.n;
